@@ -1,0 +1,201 @@
+/*
+ * grav.h - matrix-free prism-gravity operators for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the closed-form vertical attraction of rectangular
+ * prisms (paper Section 2.1, Eq. 1-3), superposed over a prism mesh (Eq. 4-6),
+ * without ever forming the sensitivity matrix G, and the data-space inversion
+ * built on it (Section 2.2, Eq. 7-11).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ * ---------------------------------------------------------------------------
+ * Geometry.  A rectilinear mesh is given by its node coordinate vectors
+ *   xn[0..nx], yn[0..ny], zn[0..nz] (metres, strictly increasing), z positive
+ *   DOWN, zn[0] = mesh top.  Cell (i, j, k) is the prism
+ *   [xn[i],xn[i+1]] x [yn[j],yn[j+1]] x [zn[k],zn[k+1]].  Flat cell index
+ *   (i*ny + j)*nz + k (C order, z fastest); M = nx*ny*nz cells.
+ * Observations.  n points (x[o], y[o], z[o]), z down; a point at height h
+ *   above the mesh top has z = zn[0] - h.  PRECONDITION: z[o] <= zn[0] (no
+ *   observation below the mesh top); the closed form used on the GPU assumes
+ *   it, and validation rejects violations with GRAV_EINVAL.
+ * Units.  Density contrast in kg/m^3, gravity in m/s^2 (1 mGal = 1e-5 m/s^2).
+ *   The constant gamma (GRAV_GAMMA) is applied in FP64.
+ * Sign.  gz > 0 means a downward pull: positive density below an observation
+ *   gives positive data (Eq. 1 with corner-minus-observation coordinates and
+ *   vertex parity (-1)^(p+q+r), vertex 1 = smaller coordinate).
+ * Memory.  EVERY array argument is a caller-owned DEVICE pointer on the
+ *   context's device (e.g. a torch tensor's data_ptr()).  The library never
+ *   frees or retains them past the completion of the work it enqueues; it
+ *   writes only the documented outputs.  Scalars marked "host" are host
+ *   memory.
+ * Streams.  Work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *   stream) in order.  With validation on (grav_ctx_opts.validate != 0, the
+ *   default) each public call first checks its arguments on the device and
+ *   waits for that check on `stream`, so the call returns only after all work
+ *   previously enqueued on `stream` has finished; with validation off the
+ *   operator calls are fully asynchronous and the caller guarantees the
+ *   preconditions.
+ * Workspace.  A context owns one device workspace allocated at creation; the
+ *   operator calls allocate nothing.  One context serves one call at a time:
+ *   calls that may overlap (different streams or threads) need separate
+ *   contexts.  grav_workspace_bytes() tells how much a call needs.
+ * Errors.  Every call returns a grav_status; no exception crosses the ABI.
+ *   On an error return nothing has been written to the outputs unless stated.
+ *   grav_last_error(ctx) gives a human-readable reason.
+ * Determinism.  No atomics are used in any reduction; results are bitwise
+ *   reproducible for the same inputs, precision and device.
+ */
+#ifndef GRAV_H
+#define GRAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRAV_GAMMA 6.674e-11   /* gravitational constant used by the workloads, SI */
+
+typedef enum {
+    GRAV_OK = 0,
+    GRAV_EINVAL = 1,    /* bad argument: null pointer, size <= 0, non-increasing nodes,
+                           observation below the mesh top, non-finite input,
+                           coordinates out of range, lambda < 0 where not allowed */
+    GRAV_ENOMEM = 2,    /* context workspace (or device memory at creation) too small */
+    GRAV_EDEVICE = 3,   /* HIP runtime error; grav_last_error() has the text */
+    GRAV_ENOCONV = 4,   /* positive warning: CG stopped at max_iter before reaching tol;
+                           all outputs are valid */
+    GRAV_EBUSY = 5      /* server: request not finished yet / queue full */
+} grav_status;
+
+typedef enum {
+    GRAV_FP64 = 0,          /* plain path: every corner term Psi(node - obs) in FP64 */
+    GRAV_MIXED = 1,         /* FP32 edge-segment terms from FP64 coordinate differences,
+                               FP64 alternating sums, accumulation and CG dot products */
+    GRAV_MIXED_BF16X3 = 2,  /* multi-model only: FP32 G tiles split into bf16 hi+lo,
+                               3-product split-BF16 MFMA, FP32 accumulation */
+    GRAV_FP32_VALU = 3      /* multi-model only: the same FP32 G tiles contracted on the
+                               FP32 vector ALUs (comparison path) */
+} grav_prec;
+
+typedef void *grav_stream;   /* a hipStream_t */
+
+/* Rectilinear prism mesh: node vectors are device pointers of nx+1, ny+1, nz+1
+ * doubles, strictly increasing, z down. */
+typedef struct {
+    int32_t nx, ny, nz;
+    const double *xn, *yn, *zn;
+} grav_mesh;
+
+/* Observation points: three device vectors of n doubles, z down. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+} grav_obs;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal */
+    int32_t validate;          /* 1 (default) = check arguments on every call, 0 = trust them */
+    uint64_t workspace_bytes;  /* device workspace owned by the context; 0 = 4 GiB */
+} grav_ctx_opts;
+
+typedef struct grav_ctx grav_ctx;
+
+/* Operation codes for grav_workspace_bytes(). */
+typedef enum {
+    GRAV_OP_FORWARD = 0, GRAV_OP_ADJOINT = 1, GRAV_OP_DATASPACE = 2, GRAV_OP_TRACE = 3,
+    GRAV_OP_INVERT = 4, GRAV_OP_FORWARD_MULTI = 5
+} grav_op;
+
+/* Fill `opts` with the defaults (device 0, validate 1, 4 GiB workspace). */
+void grav_ctx_opts_default(grav_ctx_opts *opts);
+
+/* Create a context on opts->device (NULL opts = defaults) and allocate its
+ * workspace.  *ctx receives the handle (NULL on failure).
+ * Errors: GRAV_EINVAL (ctx NULL), GRAV_ENOMEM (allocation failed),
+ * GRAV_EDEVICE (no such device / HIP failure). */
+int grav_ctx_create(grav_ctx **ctx, const grav_ctx_opts *opts);
+
+/* Release the context and its workspace (waits for the device to finish the
+ * context's work).  NULL is ignored. */
+void grav_ctx_destroy(grav_ctx *ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by the context,
+ * valid until the next call on it.  NULL ctx: the last context-creation error. */
+const char *grav_last_error(const grav_ctx *ctx);
+
+/* Device workspace bytes that `op` needs for this shape and precision (K =
+ * models for GRAV_OP_FORWARD_MULTI, ignored otherwise).  Host-only; 0 means
+ * the shape or combination is invalid. */
+uint64_t grav_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int64_t n, grav_op op,
+                              grav_prec prec, int32_t K);
+
+/* Forward product d = G m (paper Eq. 5-6; G from Eq. 1-3).
+ *   m : M doubles (density contrast, flat cell order), d : n doubles (output, m/s^2).
+ *   prec : GRAV_FP64 or GRAV_MIXED.
+ * Errors: GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE. */
+int grav_forward(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const double *m,
+                 double *d, grav_prec prec, grav_stream stream);
+
+/* Adjoint product g = G^T v (the transpose of the forward operator, which the
+ * data-space solution of Eq. 10-11 applies).
+ *   v : n doubles, g : M doubles (output).  prec : GRAV_FP64 or GRAV_MIXED. */
+int grav_adjoint(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const double *v,
+                 double *g, grav_prec prec, grav_stream stream);
+
+/* Data-space operator of Eq. 10-11: out = G C G^T v + lambda v with
+ * W_m = C = diag(wdepth^-2) (depth weights w, Li-Oldenburg) and W_d = lambda I.
+ *   wdepth : M doubles (> 0), lambda >= 0, v and out : n doubles (out may not
+ *   alias v).  prec : GRAV_FP64 or GRAV_MIXED. */
+int grav_dataspace_apply(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                         const double *wdepth, double lambda, const double *v, double *out,
+                         grav_prec prec, grav_stream stream);
+
+/* trace(G C G^T) = sum_o sum_k C_k G_ok^2 with C = diag(wdepth^-2), written to
+ * *trace (HOST pointer; the call waits for the result).  Optional `diag`
+ * (device, n doubles, may be NULL) receives the per-observation terms
+ * sum_k C_k G_ok^2, i.e. the diagonal of G C G^T.  prec : GRAV_MIXED or GRAV_FP64. */
+int grav_trace(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const double *wdepth,
+               double *trace, double *diag, grav_prec prec, grav_stream stream);
+
+/* Conjugate-gradient options for grav_invert. */
+typedef struct {
+    double tol;          /* stop when ||delta_d - A y||_2 / ||delta_d||_2 <= tol (recursive residual) */
+    int32_t max_iter;    /* iteration cap (>= 1) */
+    int32_t fixed_iters; /* > 0: run exactly this many iterations, no residual checks */
+} grav_cg_opts;
+
+typedef struct {
+    int32_t iters;       /* iterations performed */
+    double relres;       /* final ||r|| / ||delta_d|| */
+    double lambda_used;  /* lambda actually used */
+    double trace;        /* trace(G C G^T) if it was computed (lambda < 0), else 0 */
+} grav_cg_info;
+
+/* Data-space inversion (paper Eq. 10-11): delta_d = d_obs - G m_ref;
+ * solve (G C G^T + lambda I) y = delta_d by CG from y = 0; m = m_ref + C G^T y.
+ *   d_obs : n doubles; wdepth : M doubles (> 0); lambda < 0 selects
+ *   lambda = 1e-2 * trace(G C G^T) / n; m_ref : M doubles or NULL (= 0);
+ *   m_out : M doubles (output); d_pred : n doubles (output G m_out) or NULL;
+ *   info : HOST pointer or NULL.  The call waits for completion.
+ * Returns GRAV_OK, GRAV_ENOCONV (max_iter reached, outputs valid), or an error. */
+int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const double *d_obs,
+                const double *wdepth, double lambda, const double *m_ref,
+                const grav_cg_opts *cg, double *m_out, double *d_pred, grav_cg_info *info,
+                grav_prec prec, grav_stream stream);
+
+/* Multi-model forward D = G [m_1 ... m_K] (Eq. 6 for a block of models, a
+ * dense contraction over prisms).
+ *   models : M x K floats, model index fastest (models[k*K + j]);
+ *   D : n x K floats (output), model index fastest; 1 <= K <= 64.
+ *   prec : GRAV_MIXED_BF16X3 (MFMA) or GRAV_FP32_VALU. */
+int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                       const float *models, int32_t K, float *D, grav_prec prec,
+                       grav_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAV_H */

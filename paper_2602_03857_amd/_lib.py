@@ -1,0 +1,86 @@
+"""ctypes declarations of the C ABI in include/grav.h (one-to-one)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrav.so")
+
+GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV, GRAV_EBUSY = range(6)
+GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU = range(4)
+OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI = range(6)
+GRAV_GAMMA = 6.674e-11
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class CMesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("xn", ctypes.c_void_p), ("yn", ctypes.c_void_p), ("zn", ctypes.c_void_p)]
+
+
+class CObs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p)]
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("fixed_iters", ctypes.c_int32)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("lambda_used", ctypes.c_double), ("trace", ctypes.c_double)]
+
+
+class GravError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"grav error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2602_03857_amd.build` "
+            "(the gravity operators have no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                              ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "grav_ctx_opts_default": (None, [P(CtxOpts)]),
+        "grav_ctx_create": (ctypes.c_int, [P(vp), P(CtxOpts)]),
+        "grav_ctx_destroy": (None, [vp]),
+        "grav_last_error": (ctypes.c_char_p, [vp]),
+        "grav_workspace_bytes": (u64, [i32, i32, i32, i64, ctypes.c_int, ctypes.c_int, i32]),
+        "grav_forward": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, vp, ctypes.c_int, vp]),
+        "grav_adjoint": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, vp, ctypes.c_int, vp]),
+        "grav_dataspace_apply": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, dbl, vp, vp,
+                                                ctypes.c_int, vp]),
+        "grav_trace": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, P(dbl), vp, ctypes.c_int, vp]),
+        "grav_invert": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, vp, dbl, vp, P(CgOpts), vp, vp,
+                                       P(CgInfo), ctypes.c_int, vp]),
+        "grav_forward_multi": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, i32, vp, ctypes.c_int,
+                                              vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+
+EXPORTED = [
+    "grav_ctx_opts_default", "grav_ctx_create", "grav_ctx_destroy", "grav_last_error",
+    "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
+    "grav_invert", "grav_forward_multi",
+]

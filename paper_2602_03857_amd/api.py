@@ -1,0 +1,217 @@
+"""Thin Python wrappers over the C ABI: device tensors in, device tensors out.
+
+Each method checks dtypes/devices, passes raw device pointers and the current
+torch stream to the library, and raises ``GravError`` on a non-OK status.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import (lib, GravError, CMesh, CObs, CtxOpts, CgOpts, CgInfo, GRAV_OK, GRAV_ENOCONV,
+                   GRAV_MIXED, GRAV_MIXED_BF16X3, OP_FORWARD)
+
+
+def _device_f64(a, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+    return t.contiguous()
+
+
+def _check(t: torch.Tensor, dtype, numel: int, name: str, device) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise TypeError(f"{name} must live on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+class DeviceMesh:
+    """Node coordinate vectors resident on the device (float64, z down)."""
+
+    def __init__(self, xn, yn, zn, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.xn = _device_f64(xn, self.device)
+        self.yn = _device_f64(yn, self.device)
+        self.zn = _device_f64(zn, self.device)
+        self.nx, self.ny, self.nz = self.xn.numel() - 1, self.yn.numel() - 1, self.zn.numel() - 1
+        self.c = CMesh(self.nx, self.ny, self.nz, self.xn.data_ptr(), self.yn.data_ptr(),
+                       self.zn.data_ptr())
+
+    @classmethod
+    def from_mesh(cls, mesh, device="cuda") -> "DeviceMesh":
+        return cls(mesh.xn, mesh.yn, mesh.zn, device)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+class DeviceObs:
+    """Observation points resident on the device (float64, z down)."""
+
+    def __init__(self, x, y, z, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.x = _device_f64(x, self.device)
+        self.y = _device_f64(y, self.device)
+        self.z = _device_f64(z, self.device)
+        self.n = self.x.numel()
+        self.c = CObs(self.n, self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr())
+
+    @classmethod
+    def from_survey(cls, obs, device="cuda") -> "DeviceObs":
+        return cls(obs.x, obs.y, obs.z, device)
+
+
+def workspace_bytes(nx, ny, nz, n, op=OP_FORWARD, prec=GRAV_MIXED, K=0) -> int:
+    return int(lib.grav_workspace_bytes(nx, ny, nz, n, op, prec, K))
+
+
+class Context:
+    """A library context: one device, one workspace, one call at a time."""
+
+    def __init__(self, device: int = 0, validate: bool = True, workspace_bytes: int = 0):
+        opts = CtxOpts()
+        lib.grav_ctx_opts_default(ctypes.byref(opts))
+        opts.device = device
+        opts.validate = 1 if validate else 0
+        opts.workspace_bytes = workspace_bytes
+        h = ctypes.c_void_p()
+        rc = lib.grav_ctx_create(ctypes.byref(h), ctypes.byref(opts))
+        if rc != GRAV_OK:
+            raise GravError(rc, lib.grav_last_error(None).decode())
+        self._h = h
+        self.device = torch.device("cuda", device)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.grav_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def last_error(self) -> str:
+        return lib.grav_last_error(self._h).decode()
+
+    def _rc(self, rc: int, allow_noconv: bool = False) -> int:
+        if rc == GRAV_OK or (allow_noconv and rc == GRAV_ENOCONV):
+            return rc
+        raise GravError(rc, self.last_error())
+
+    def _stream(self, stream):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    # ------------------------------------------------------------ operators
+    def forward(self, mesh: DeviceMesh, obs: DeviceObs, m, d=None, prec=GRAV_MIXED, stream=None):
+        """d = G m.  m: (M,) float64 device tensor."""
+        _check(m, torch.float64, mesh.ncells, "m", self.device)
+        if d is None:
+            d = torch.empty(obs.n, dtype=torch.float64, device=self.device)
+        _check(d, torch.float64, obs.n, "d", self.device)
+        self._rc(lib.grav_forward(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
+                                  m.data_ptr(), d.data_ptr(), prec, self._stream(stream)))
+        return d
+
+    def adjoint(self, mesh: DeviceMesh, obs: DeviceObs, v, g=None, prec=GRAV_MIXED, stream=None):
+        """g = G^T v.  v: (n,) float64 device tensor."""
+        _check(v, torch.float64, obs.n, "v", self.device)
+        if g is None:
+            g = torch.empty(mesh.ncells, dtype=torch.float64, device=self.device)
+        _check(g, torch.float64, mesh.ncells, "g", self.device)
+        self._rc(lib.grav_adjoint(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
+                                  v.data_ptr(), g.data_ptr(), prec, self._stream(stream)))
+        return g
+
+    def dataspace_apply(self, mesh, obs, wdepth, lam, v, out=None, prec=GRAV_MIXED, stream=None):
+        """out = G diag(wdepth^-2) G^T v + lam v."""
+        _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
+        _check(v, torch.float64, obs.n, "v", self.device)
+        if out is None:
+            out = torch.empty(obs.n, dtype=torch.float64, device=self.device)
+        _check(out, torch.float64, obs.n, "out", self.device)
+        self._rc(lib.grav_dataspace_apply(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
+                                          wdepth.data_ptr(), float(lam), v.data_ptr(),
+                                          out.data_ptr(), prec, self._stream(stream)))
+        return out
+
+    def trace(self, mesh, obs, wdepth, diag=None, prec=GRAV_MIXED, stream=None):
+        """trace(G C G^T); fills `diag` (n,) with the per-observation terms if given."""
+        _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
+        if diag is not None:
+            _check(diag, torch.float64, obs.n, "diag", self.device)
+        tr = ctypes.c_double()
+        self._rc(lib.grav_trace(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
+                                wdepth.data_ptr(), ctypes.byref(tr),
+                                diag.data_ptr() if diag is not None else None, prec,
+                                self._stream(stream)))
+        return tr.value
+
+    def invert(self, mesh, obs, d_obs, wdepth, lam=-1.0, m_ref=None, tol=1e-6, max_iter=200,
+               fixed_iters=0, m_out=None, d_pred=None, want_pred=False, prec=GRAV_MIXED,
+               stream=None):
+        """Data-space CG inversion (Eq. 11).  Returns (m, d_pred or None, info dict)."""
+        _check(d_obs, torch.float64, obs.n, "d_obs", self.device)
+        _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
+        if m_ref is not None:
+            _check(m_ref, torch.float64, mesh.ncells, "m_ref", self.device)
+        if m_out is None:
+            m_out = torch.empty(mesh.ncells, dtype=torch.float64, device=self.device)
+        _check(m_out, torch.float64, mesh.ncells, "m_out", self.device)
+        if d_pred is None and want_pred:
+            d_pred = torch.empty(obs.n, dtype=torch.float64, device=self.device)
+        if d_pred is not None:
+            _check(d_pred, torch.float64, obs.n, "d_pred", self.device)
+        cg = CgOpts(float(tol), int(max_iter), int(fixed_iters))
+        info = CgInfo()
+        rc = lib.grav_invert(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c), d_obs.data_ptr(),
+                             wdepth.data_ptr(), float(lam),
+                             m_ref.data_ptr() if m_ref is not None else None, ctypes.byref(cg),
+                             m_out.data_ptr(), d_pred.data_ptr() if d_pred is not None else None,
+                             ctypes.byref(info), prec, self._stream(stream))
+        self._rc(rc, allow_noconv=True)
+        return m_out, d_pred, dict(iters=info.iters, relres=info.relres,
+                                   lambda_used=info.lambda_used, trace=info.trace,
+                                   converged=(rc == GRAV_OK))
+
+    def forward_multi(self, mesh, obs, models, D=None, prec=GRAV_MIXED_BF16X3, stream=None):
+        """D = G M for models (M, K) float32 (model index fastest); returns (n, K) float32."""
+        if models.dim() != 2:
+            raise ValueError("models must be (M, K)")
+        K = models.shape[1]
+        _check(models, torch.float32, mesh.ncells * K, "models", self.device)
+        if D is None:
+            D = torch.empty((obs.n, K), dtype=torch.float32, device=self.device)
+        _check(D, torch.float32, obs.n * K, "D", self.device)
+        self._rc(lib.grav_forward_multi(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
+                                        models.data_ptr(), K, D.data_ptr(), prec,
+                                        self._stream(stream)))
+        return D

@@ -1,0 +1,370 @@
+// C-ABI entry points of the gravity library (declared in include/grav.h):
+// argument checks, device-side validation, workspace carving, and the
+// composition of the sweep kernels into the forward, adjoint and data-space
+// operators and the data-space CG inversion (paper Eq. 5-11).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "grav_internal.h"
+#include "api_internal.h"
+
+using namespace grav;
+
+static thread_local std::string g_create_error;
+
+// ---------------------------------------------------------------- helpers
+
+namespace grav {
+
+int fail(grav_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(grav_ctx *ctx, hipError_t e, const char *where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(ctx, GRAV_EDEVICE, m);
+}
+
+Arena ctx_arena(grav_ctx *ctx) {
+    Arena a;
+    a.base = ctx->ws + kReserveBytes;
+    a.size = ctx->ws_bytes > kReserveBytes ? ctx->ws_bytes - kReserveBytes : 0;
+    return a;
+}
+
+int check_geometry_host(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs) {
+    if (!mesh || !obs) return fail(ctx, GRAV_EINVAL, "mesh or obs is NULL");
+    if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0)
+        return fail(ctx, GRAV_EINVAL, "mesh dimensions must be positive");
+    if (!mesh->xn || !mesh->yn || !mesh->zn) return fail(ctx, GRAV_EINVAL, "mesh node vector is NULL");
+    if (obs->n <= 0) return fail(ctx, GRAV_EINVAL, "observation count must be positive");
+    if (obs->n > (int64_t)1 << 31) return fail(ctx, GRAV_EINVAL, "more than 2^31 observations");
+    if (!obs->x || !obs->y || !obs->z) return fail(ctx, GRAV_EINVAL, "observation vector is NULL");
+    const int64_t segs = (int64_t)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1);
+    if (segs > ((int64_t)1 << 40)) return fail(ctx, GRAV_EINVAL, "mesh too large");
+    return GRAV_OK;
+}
+
+static const char *flag_text(int f) {
+    if (f & kBadMesh) return "mesh node coordinates must be finite and strictly increasing";
+    if (f & kBadObs) return "observation coordinates must be finite";
+    if (f & kObsBelowTop) return "observation below the mesh top (z > zn[0])";
+    if (f & kOutOfRange) return "node-observation distance above 1e6 m";
+    if (f & kBadWeights) return "depth weights must be finite and > 0";
+    if (f & kBadValues) return "input vector has non-finite values";
+    return "invalid input";
+}
+
+int validate_on_device(grav_ctx *ctx, const Mesh &g, const Obs &o, hipStream_t st,
+                       std::initializer_list<ArrayCheck> arrays) {
+    if (!ctx->validate) return GRAV_OK;
+    int *flags = reinterpret_cast<int *>(ctx->ws);
+    hipError_t e = hipMemsetAsync(flags, 0, sizeof(int), st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "validate memset");
+    e = launch_validate(g, o, flags, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "validate launch");
+    for (const ArrayCheck &a : arrays) {
+        if (!a.ptr) continue;
+        e = a.positive ? launch_validate_positive(a.ptr, a.len, flags, st)
+                       : launch_validate_finite(a.ptr, a.len, flags, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "validate launch");
+    }
+    e = hipMemcpyAsync(ctx->h_flags, flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "validate copy");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "validate sync");
+    const int f = *ctx->h_flags;
+    if (f) return fail(ctx, GRAV_EINVAL, flag_text(f));
+    return GRAV_OK;
+}
+
+// ---------------------------------------------------------------- operators
+
+#define HIP_TRY(expr, where)                                       \
+    do {                                                           \
+        hipError_t _e = (expr);                                    \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, where);     \
+    } while (0)
+
+// d = scale * sum_parts + coef * add
+int op_forward(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *m, double *d,
+               grav_prec prec, hipStream_t st, double scale, const double *add, double coef) {
+    const ForwardPlan fp = plan_forward(g.ncols(), o.n);
+    const size_t mark = ar.off;
+    double *part = ar.take<double>((size_t)fp.nchunk * o.n);
+    if (prec == GRAV_MIXED) {
+        float *hk = ar.take<float>(g.nz);
+        double *w2 = ar.take<double>(g.nsegs());
+        if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the forward sweep");
+        HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
+        HIP_TRY(launch_edge_weights(g, m, w2, st), "edge weights");
+        HIP_TRY(launch_forward_mixed(g, o, hk, w2, fp, part, st), "forward sweep");
+    } else {
+        double *wn = ar.take<double>(g.nnodes());
+        if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the forward sweep");
+        HIP_TRY(launch_node_weights(g, m, wn, st), "node weights");
+        HIP_TRY(launch_forward_f64(g, o, wn, fp, part, st), "forward sweep");
+    }
+    HIP_TRY(launch_reduce_parts(part, fp.nchunk, o.n, scale, add, coef, d, st), "forward reduce");
+    ar.off = mark;
+    return GRAV_OK;
+}
+
+// out = base + scale * C * G^T v / gamma-free (scale carries gamma)
+int op_adjoint(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *v, double *out,
+               grav_prec prec, hipStream_t st, double scale, const double *wdepth,
+               const double *base) {
+    const size_t mark = ar.off;
+    if (prec == GRAV_MIXED) {
+        const AdjointPlan ap = plan_adjoint(g.ncols(), g.nz, o.n);
+        float *hk = ar.take<float>(g.nz);
+        double *upart = ar.take<double>((size_t)ap.nparts * g.nsegs());
+        double *U = ar.take<double>(g.nsegs());
+        if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the adjoint sweep");
+        HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
+        HIP_TRY(launch_adjoint_mixed(g, o, hk, v, ap, upart, st), "adjoint sweep");
+        HIP_TRY(launch_reduce_parts(upart, ap.nparts, g.nsegs(), 1.0, nullptr, 0.0, U, st),
+                "adjoint reduce");
+        HIP_TRY(launch_adjoint_finish_edges(g, U, scale, wdepth, base, out, st), "adjoint finish");
+    } else {
+        const NodeAdjointPlan ap = plan_adjoint_nodes(g.nnodes(), o.n);
+        double *ppart = ar.take<double>((size_t)ap.nparts * g.nnodes());
+        double *P = ar.take<double>(g.nnodes());
+        if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the adjoint sweep");
+        HIP_TRY(launch_adjoint_f64(g, o, v, ap, ppart, st), "adjoint sweep");
+        HIP_TRY(launch_reduce_parts(ppart, ap.nparts, g.nnodes(), 1.0, nullptr, 0.0, P, st),
+                "adjoint reduce");
+        HIP_TRY(launch_adjoint_finish_nodes(g, P, scale, wdepth, base, out, st), "adjoint finish");
+    }
+    ar.off = mark;
+    return GRAV_OK;
+}
+
+// out = G C G^T v + lambda v
+int op_dataspace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
+                 double lambda, const double *v, double *out, grav_prec prec, hipStream_t st) {
+    const size_t mark = ar.off;
+    double *t = ar.take<double>(g.ncells());
+    if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the data-space operator");
+    int rc = op_adjoint(ctx, ar, g, o, v, t, prec, st, GRAV_GAMMA, wdepth, nullptr);
+    if (rc) return rc;
+    rc = op_forward(ctx, ar, g, o, t, out, prec, st, GRAV_GAMMA, v, lambda);
+    if (rc) return rc;
+    ar.off = mark;
+    return GRAV_OK;
+}
+
+// diag (device, may be null) and the trace (host)
+int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
+             double *trace, double *diag, grav_prec prec, hipStream_t st) {
+    const size_t mark = ar.off;
+    const ForwardPlan tp = plan_trace(g.nx, o.n);
+    double *part = ar.take<double>((size_t)tp.nchunk * o.n);
+    double *dg = diag ? diag : ar.take<double>(o.n);
+    float *hk = ar.take<float>(g.nz);
+    if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the trace sweep");
+    if (prec == GRAV_MIXED) {
+        HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
+        HIP_TRY(launch_trace_mixed(g, o, hk, wdepth, tp, part, st), "trace sweep");
+    } else {
+        HIP_TRY(launch_trace_f64(g, o, wdepth, tp, part, st), "trace sweep");
+    }
+    HIP_TRY(launch_reduce_parts(part, tp.nchunk, o.n, GRAV_GAMMA * GRAV_GAMMA, nullptr, 0.0, dg, st),
+            "trace reduce");
+    double *scal = ctx_scalars(ctx);
+    double *dpart = ctx_dot_partials(ctx);
+    HIP_TRY(launch_dot(dg, nullptr, o.n, dpart, st), "trace sum");
+    HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kNumScalars - 1, st), "trace sum");
+    HIP_TRY(hipMemcpyAsync(ctx->h_scal, scal, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, st),
+            "trace copy");
+    HIP_TRY(hipStreamSynchronize(st), "trace sync");
+    *trace = ctx->h_scal[kNumScalars - 1];
+    ar.off = mark;
+    return GRAV_OK;
+}
+
+}  // namespace grav
+
+// ---------------------------------------------------------------- context
+
+extern "C" void grav_ctx_opts_default(grav_ctx_opts *opts) {
+    if (!opts) return;
+    opts->device = 0;
+    opts->validate = 1;
+    opts->workspace_bytes = 0;
+}
+
+extern "C" int grav_ctx_create(grav_ctx **out, const grav_ctx_opts *opts_in) {
+    if (!out) return GRAV_EINVAL;
+    *out = nullptr;
+    grav_ctx_opts opts;
+    grav_ctx_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.workspace_bytes == 0) opts.workspace_bytes = (uint64_t)4 << 30;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        g_create_error = "no HIP device available";
+        return GRAV_EDEVICE;
+    }
+    if (opts.device < 0 || opts.device >= ndev) {
+        g_create_error = "device ordinal out of range";
+        return GRAV_EINVAL;
+    }
+    e = hipSetDevice(opts.device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return GRAV_EDEVICE;
+    }
+    grav_ctx *ctx = new grav_ctx();
+    ctx->device = opts.device;
+    ctx->validate = opts.validate != 0;
+    ctx->ws_bytes = (size_t)opts.workspace_bytes + kReserveBytes;
+    e = hipMalloc(reinterpret_cast<void **>(&ctx->ws), ctx->ws_bytes);
+    if (e != hipSuccess) {
+        g_create_error = std::string("workspace allocation: ") + hipGetErrorString(e);
+        delete ctx;
+        return GRAV_ENOMEM;
+    }
+    e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_pinned), 4096, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        g_create_error = std::string("pinned allocation: ") + hipGetErrorString(e);
+        (void)hipFree(ctx->ws);
+        delete ctx;
+        return GRAV_ENOMEM;
+    }
+    ctx->h_flags = reinterpret_cast<int *>(ctx->h_pinned);
+    ctx->h_scal = reinterpret_cast<double *>(ctx->h_pinned + 256);
+    *out = ctx;
+    return GRAV_OK;
+}
+
+extern "C" void grav_ctx_destroy(grav_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ws);
+    (void)hipHostFree(ctx->h_pinned);
+    delete ctx;
+}
+
+extern "C" const char *grav_last_error(const grav_ctx *ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+extern "C" uint64_t grav_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int64_t n, grav_op op,
+                                         grav_prec prec, int32_t K) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || n <= 0) return 0;
+    return grav::workspace_need(nx, ny, nz, n, op, prec, K);
+}
+
+// ---------------------------------------------------------------- operators
+
+#define ENTER(ctx)                                          \
+    if (!(ctx)) return GRAV_EINVAL;                         \
+    (ctx)->err.clear();                                     \
+    do {                                                    \
+        hipError_t _e = hipSetDevice((ctx)->device);        \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, "hipSetDevice"); \
+    } while (0)
+
+static inline Mesh to_mesh(const grav_mesh *m) { return Mesh{m->nx, m->ny, m->nz, m->xn, m->yn, m->zn}; }
+static inline Obs to_obs(const grav_obs *o) { return Obs{o->n, o->x, o->y, o->z}; }
+
+extern "C" int grav_forward(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                            const double *m, double *d, grav_prec prec, grav_stream stream) {
+    ENTER(ctx);
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!m || !d) return fail(ctx, GRAV_EINVAL, "m or d is NULL");
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st, {ArrayCheck{m, g.ncells(), false}});
+    if (rc) return rc;
+    Arena ar = ctx_arena(ctx);
+    return op_forward(ctx, ar, g, o, m, d, prec, st, GRAV_GAMMA, nullptr, 0.0);
+}
+
+extern "C" int grav_adjoint(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                            const double *v, double *gout, grav_prec prec, grav_stream stream) {
+    ENTER(ctx);
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!v || !gout) return fail(ctx, GRAV_EINVAL, "v or g is NULL");
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st, {ArrayCheck{v, o.n, false}});
+    if (rc) return rc;
+    Arena ar = ctx_arena(ctx);
+    return op_adjoint(ctx, ar, g, o, v, gout, prec, st, GRAV_GAMMA, nullptr, nullptr);
+}
+
+extern "C" int grav_dataspace_apply(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                                    const double *wdepth, double lambda, const double *v,
+                                    double *out, grav_prec prec, grav_stream stream) {
+    ENTER(ctx);
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!wdepth || !v || !out) return fail(ctx, GRAV_EINVAL, "wdepth, v or out is NULL");
+    if (v == out) return fail(ctx, GRAV_EINVAL, "out may not alias v");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(ctx, GRAV_EINVAL, "lambda must be finite and >= 0");
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st,
+                            {ArrayCheck{wdepth, g.ncells(), true}, ArrayCheck{v, o.n, false}});
+    if (rc) return rc;
+    Arena ar = ctx_arena(ctx);
+    return op_dataspace(ctx, ar, g, o, wdepth, lambda, v, out, prec, st);
+}
+
+extern "C" int grav_trace(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                          const double *wdepth, double *trace, double *diag, grav_prec prec,
+                          grav_stream stream) {
+    ENTER(ctx);
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!wdepth || !trace) return fail(ctx, GRAV_EINVAL, "wdepth or trace is NULL");
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st, {ArrayCheck{wdepth, g.ncells(), true}});
+    if (rc) return rc;
+    Arena ar = ctx_arena(ctx);
+    return op_trace(ctx, ar, g, o, wdepth, trace, diag, prec, st);
+}
+
+extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                           const double *d_obs, const double *wdepth, double lambda,
+                           const double *m_ref, const grav_cg_opts *cg, double *m_out,
+                           double *d_pred, grav_cg_info *info, grav_prec prec,
+                           grav_stream stream) {
+    ENTER(ctx);
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!d_obs || !wdepth || !cg || !m_out) return fail(ctx, GRAV_EINVAL, "d_obs, wdepth, cg or m_out is NULL");
+    if (!std::isfinite(lambda)) return fail(ctx, GRAV_EINVAL, "lambda must be finite");
+    if (cg->fixed_iters <= 0 && (cg->max_iter < 1 || !(cg->tol >= 0.0)))
+        return fail(ctx, GRAV_EINVAL, "CG needs max_iter >= 1 and tol >= 0, or fixed_iters > 0");
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st,
+                            {ArrayCheck{wdepth, g.ncells(), true}, ArrayCheck{d_obs, o.n, false},
+                             ArrayCheck{m_ref, g.ncells(), false}});
+    if (rc) return rc;
+    return grav::run_invert(ctx, g, o, d_obs, wdepth, lambda, m_ref, *cg, m_out, d_pred, info, prec, st);
+}

@@ -1,0 +1,180 @@
+// Data-space inversion (paper Section 2.2, Eq. 10-11) with conjugate
+// gradients on the N x N system (G C G^T + lambda I) y = delta_d, the
+// operator applied matrix-free by the sweeps, all vectors and scalars on the
+// device.  Also the workspace sizing shared by every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "api_internal.h"
+
+namespace grav {
+
+#define HIP_TRY(expr, where)                                       \
+    do {                                                           \
+        hipError_t _e = (expr);                                    \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, where);     \
+    } while (0)
+
+static int read_scalars(grav_ctx *ctx, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_scal, ctx_scalars(ctx), kNumScalars * sizeof(double),
+                           hipMemcpyDeviceToHost, st), "scalar copy");
+    HIP_TRY(hipStreamSynchronize(st), "scalar sync");
+    return GRAV_OK;
+}
+
+int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
+               const double *wdepth, double lambda, const double *m_ref, const grav_cg_opts &cg,
+               double *m_out, double *d_pred, grav_cg_info *info, grav_prec prec, hipStream_t st) {
+    Arena ar = ctx_arena(ctx);
+    const int64_t n = o.n;
+    double *y = ar.take<double>(n);
+    double *r = ar.take<double>(n);
+    double *p = ar.take<double>(n);
+    double *q = ar.take<double>(n);
+    if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the CG vectors");
+    double *scal = ctx_scalars(ctx);
+    double *dpart = ctx_dot_partials(ctx);
+
+    double trace = 0.0;
+    if (lambda < 0.0) {   // lambda = 1e-2 * trace(G C G^T) / n
+        int rc = op_trace(ctx, ar, g, o, wdepth, &trace, nullptr, prec, st);
+        if (rc) return rc;
+        lambda = 1e-2 * trace / (double)n;
+    }
+
+    // r = delta_d = d_obs - G m_ref ; p = r ; y = 0
+    if (m_ref) {
+        int rc = op_forward(ctx, ar, g, o, m_ref, r, prec, st, -GRAV_GAMMA, d_obs, 1.0);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(launch_sub(d_obs, nullptr, r, n, st), "copy");
+    }
+    HIP_TRY(launch_sub(r, nullptr, p, n, st), "copy");
+    HIP_TRY(launch_fill(y, 0.0, n, st), "fill");
+    HIP_TRY(launch_dot(r, r, n, dpart, st), "dot");
+    HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+    int rc = read_scalars(ctx, st);
+    if (rc) return rc;
+    const double b2 = ctx->h_scal[kB2];
+
+    const bool fixed = cg.fixed_iters > 0;
+    const int iters_cap = fixed ? cg.fixed_iters : cg.max_iter;
+    int it = 0;
+    double relres = b2 > 0.0 ? 1.0 : 0.0;
+    bool converged = b2 == 0.0;
+    for (it = 0; it < iters_cap && !converged;) {
+        rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
+        if (rc) return rc;
+        HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
+        HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQ, 0, st), "dot");
+        HIP_TRY(launch_cg_update_yr(y, r, p, q, n, scal, dpart, st), "cg update");
+        HIP_TRY(launch_dot_finish(dpart, scal, kFinishRRNew, 0, st), "dot");
+        ++it;
+        if (!fixed) {
+            rc = read_scalars(ctx, st);
+            if (rc) return rc;
+            relres = std::sqrt(ctx->h_scal[kRR] / b2);
+            if (relres <= cg.tol) { converged = true; break; }
+        }
+        HIP_TRY(launch_cg_update_p(p, r, n, scal, st), "cg update");
+    }
+    if (fixed && b2 > 0.0) {
+        rc = read_scalars(ctx, st);
+        if (rc) return rc;
+        relres = std::sqrt(ctx->h_scal[kRR] / b2);
+    }
+
+    // m = m_ref + C G^T y ; optional predicted data
+    rc = op_adjoint(ctx, ar, g, o, y, m_out, prec, st, GRAV_GAMMA, wdepth, m_ref);
+    if (rc) return rc;
+    if (d_pred) {
+        rc = op_forward(ctx, ar, g, o, m_out, d_pred, prec, st, GRAV_GAMMA, nullptr, 0.0);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipStreamSynchronize(st), "final sync");
+    if (info) {
+        info->iters = it;
+        info->relres = relres;
+        info->lambda_used = lambda;
+        info->trace = trace;
+    }
+    if (!fixed && !converged) {
+        ctx->err = "CG reached max_iter before tol";
+        return GRAV_ENOCONV;
+    }
+    return GRAV_OK;
+}
+
+// ------------------------------------------------------------------ sizing
+
+static size_t need_forward(const Mesh &g, int64_t n, grav_prec prec) {
+    Counter c;
+    const ForwardPlan fp = plan_forward(g.ncols(), n);
+    c.take<double>((size_t)fp.nchunk * n);
+    if (prec == GRAV_MIXED) {
+        c.take<float>(g.nz);
+        c.take<double>(g.nsegs());
+    } else {
+        c.take<double>(g.nnodes());
+    }
+    return c.off;
+}
+
+static size_t need_adjoint(const Mesh &g, int64_t n, grav_prec prec) {
+    Counter c;
+    if (prec == GRAV_MIXED) {
+        const AdjointPlan ap = plan_adjoint(g.ncols(), g.nz, n);
+        c.take<float>(g.nz);
+        c.take<double>((size_t)ap.nparts * g.nsegs());
+        c.take<double>(g.nsegs());
+    } else {
+        const NodeAdjointPlan ap = plan_adjoint_nodes(g.nnodes(), n);
+        c.take<double>((size_t)ap.nparts * g.nnodes());
+        c.take<double>(g.nnodes());
+    }
+    return c.off;
+}
+
+static size_t need_trace(const Mesh &g, int64_t n) {
+    Counter c;
+    const ForwardPlan tp = plan_trace(g.nx, n);
+    c.take<double>((size_t)tp.nchunk * n);
+    c.take<double>(n);
+    c.take<float>(g.nz);
+    return c.off;
+}
+
+static size_t need_dataspace(const Mesh &g, int64_t n, grav_prec prec) {
+    Counter c;
+    c.take<double>(g.ncells());
+    const size_t a = need_adjoint(g, n, prec), f = need_forward(g, n, prec);
+    return c.off + (a > f ? a : f);
+}
+
+uint64_t workspace_need(int nx, int ny, int nz, int64_t n, grav_op op, grav_prec prec, int K) {
+    const Mesh g{nx, ny, nz, nullptr, nullptr, nullptr};
+    switch (op) {
+        case GRAV_OP_FORWARD:
+            return need_forward(g, n, prec);
+        case GRAV_OP_ADJOINT:
+            return need_adjoint(g, n, prec);
+        case GRAV_OP_DATASPACE:
+            return need_dataspace(g, n, prec);
+        case GRAV_OP_TRACE:
+            return need_trace(g, n);
+        case GRAV_OP_INVERT: {
+            Counter c;
+            for (int i = 0; i < 4; ++i) c.take<double>(n);
+            size_t inner = need_dataspace(g, n, prec);
+            const size_t t = need_trace(g, n);
+            if (t > inner) inner = t;
+            return c.off + inner;
+        }
+        case GRAV_OP_FORWARD_MULTI:
+            return multi_workspace_need(g, n, prec, K);
+    }
+    return 0;
+}
+
+}  // namespace grav

@@ -1,0 +1,69 @@
+"""Write stored FP64 oracle values for the large workloads (tests/golden/*.npz).
+
+Calls only ``oracle`` (and the seeded input generators in ``workloads``).
+Run from the repository root:  python tests/golden/make_golden.py [which ...]
+
+* config4_rows.npz : d = G m at 2,000 seeded observation rows of the
+  178,797 x 3,307,500 paper-scale workload (seed 12345 picks the rows), and
+  (G^T v) at 48 seeded cells for the workload's probe vector v.
+* config2_rows.npz : d = G m at 256 rows and (G^T v) at 64 cells of the
+  10,000 x 500,000 forward/adjoint workload.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import prism, parallel  # noqa: E402
+import workloads  # noqa: E402
+
+
+def _adjoint_cells_parallel(mesh, obs, v, cells, workers):
+    import multiprocessing as mp
+    chunks = np.array_split(np.asarray(cells), workers)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        parts = pool.starmap(prism.adjoint_cells, [(mesh, obs, v, c) for c in chunks])
+    return np.concatenate(parts)
+
+
+def make_config4(workers):
+    p = workloads.config4()
+    rng = np.random.default_rng(12345)
+    rows = np.sort(rng.choice(p.obs.n, 2000, replace=False))
+    cells = np.sort(rng.choice(p.mesh.ncells, 48, replace=False))
+    t = time.time()
+    d = parallel.forward_rows(p.mesh, p.obs, p.m, rows, workers=workers)
+    print(f"config4 rows: {time.time() - t:.1f} s", flush=True)
+    t = time.time()
+    g = _adjoint_cells_parallel(p.mesh, p.obs, p.probe_v, cells, workers)
+    print(f"config4 cells: {time.time() - t:.1f} s", flush=True)
+    np.savez(os.path.join(HERE, "config4_rows.npz"), rows=rows, d=d, cells=cells, gtv=g)
+
+
+def make_config2(workers):
+    p = workloads.config2()
+    rng = np.random.default_rng(2222)
+    rows = np.sort(rng.choice(p.obs.n, 256, replace=False))
+    cells = np.sort(rng.choice(p.mesh.ncells, 64, replace=False))
+    t = time.time()
+    d = parallel.forward_rows(p.mesh, p.obs, p.m, rows, workers=workers)
+    g = _adjoint_cells_parallel(p.mesh, p.obs, p.probe_v, cells, workers)
+    print(f"config2: {time.time() - t:.1f} s", flush=True)
+    np.savez(os.path.join(HERE, "config2_rows.npz"), rows=rows, d=d, cells=cells, gtv=g)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["config2", "config4"]
+    w = parallel.default_workers()
+    if "config2" in which:
+        make_config2(w)
+    if "config4" in which:
+        make_config4(w)

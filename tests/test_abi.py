@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports every entry point include/grav.h
+declares; host-only calls behave (no compute calls: CPU only)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from tests._util import load_package, ROOT
+
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def _declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(grav_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_operator_entry_points():
+    names = _declared_functions()
+    for required in ("grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_invert",
+                     "grav_trace", "grav_forward_multi", "grav_ctx_create", "grav_ctx_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    g = load_package()
+    names = _declared_functions()
+    for n in names:
+        assert hasattr(g.lib, n), f"{n} declared in a header but not exported"
+    out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (grav_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_workspace_query_is_host_only_and_sane():
+    g = load_package()
+    f = g.workspace_bytes(150, 150, 147, 178_797, g.OP_FORWARD, g.GRAV_MIXED)
+    segs = 151 * 151 * 147
+    assert segs * 8 <= f <= 2 * 1024 ** 3
+    inv = g.workspace_bytes(150, 150, 147, 178_797, g.OP_INVERT, g.GRAV_MIXED)
+    assert inv > f
+    assert g.workspace_bytes(0, 1, 1, 1, g.OP_FORWARD, g.GRAV_MIXED) == 0
+    assert g.workspace_bytes(4, 4, 4, 10, g.OP_DATASPACE, g.GRAV_FP64) > 0
+
+
+def test_context_creation_reports_missing_device_or_succeeds():
+    g = load_package()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; covered by the GPU tests")
+    with pytest.raises(g.GravError) as e:
+        g.Context()
+    assert e.value.code == g.GRAV_EDEVICE
+    assert g.lib.grav_forward(None, None, None, None, None, 1, None) == g.GRAV_EINVAL
+    assert g.lib.grav_last_error(None) is not None
+
+
+def test_opts_default():
+    g = load_package()
+    o = g.CtxOpts()
+    g.lib.grav_ctx_opts_default(ctypes.byref(o))
+    assert o.device == 0 and o.validate == 1 and o.workspace_bytes == 0

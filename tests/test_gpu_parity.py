@@ -1,0 +1,299 @@
+"""GPU parity: the HIP operators (called through the C ABI) against the FP64
+CPU oracle on the same seeded inputs.
+
+Tolerances: GRAV_FP64 to 1e-10 relative L2 (both are FP64; only summation
+order differs); GRAV_MIXED to 1e-5 relative L2 for gz (the accuracy target of
+the mixed path) and 1e-4 relative L2 for the recovered density."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import prism, inversion, GAMMA
+import workloads
+from tests._util import load_package, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-10
+TOL_MIXED = 1e-5
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def g():
+    pkg = load_package()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(device=0)
+    yield c
+    c.close()
+
+
+def _dev(g, p):
+    return g.DeviceMesh.from_mesh(p.mesh), g.DeviceObs.from_survey(p.obs)
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _report(name, err):
+    print(f"[parity] {name}: rel L2 = {err:.3e}", flush=True)
+
+
+# ------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+@pytest.mark.parametrize("case", [
+    dict(seed=1, nx=13, ny=11, nz=7, n=333, on_nodes=20, on_top=40),
+    dict(seed=2, nx=5, ny=3, nz=2, n=1, on_nodes=0, on_top=0),
+    dict(seed=3, nx=1, ny=1, nz=1, n=65, on_nodes=10, on_top=10),
+    dict(seed=4, nx=40, ny=9, nz=33, n=257, on_nodes=30, on_top=30),
+])
+def test_forward_random_ragged(g, ctx, prec_name, case):
+    p = workloads.random_case(case["seed"], case["nx"], case["ny"], case["nz"], case["n"],
+                              on_nodes=case["on_nodes"], on_top=case["on_top"])
+    mesh, obs = _dev(g, p)
+    d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=getattr(g, prec_name)))
+    ref = prism.forward(p.mesh, p.obs, p.m)
+    err = rel_l2(d, ref)
+    _report(f"forward {prec_name} {case}", err)
+    assert err <= (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED)
+    assert np.all(np.isfinite(d))
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_forward_config1(g, ctx, prec_name):
+    p = workloads.config1()
+    mesh, obs = _dev(g, p)
+    d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=getattr(g, prec_name)))
+    ref = prism.forward(p.mesh, p.obs, p.m)
+    err = rel_l2(d, ref)
+    _report(f"forward config1 {prec_name}", err)
+    assert err <= (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED)
+    assert np.max(np.abs(d - ref)) <= 10 * (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED) * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------ adjoint
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+@pytest.mark.parametrize("case", [
+    dict(seed=5, nx=13, ny=11, nz=7, n=333, on_nodes=20, on_top=40),
+    dict(seed=6, nx=31, ny=17, nz=19, n=70, on_nodes=5, on_top=5),
+    dict(seed=7, nx=2, ny=3, nz=1, n=1, on_nodes=1, on_top=1),
+])
+def test_adjoint_random_ragged(g, ctx, prec_name, case):
+    p = workloads.random_case(case["seed"], case["nx"], case["ny"], case["nz"], case["n"],
+                              on_nodes=case["on_nodes"], on_top=case["on_top"])
+    mesh, obs = _dev(g, p)
+    gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=getattr(g, prec_name)))
+    ref = prism.adjoint(p.mesh, p.obs, p.probe_v)
+    err = rel_l2(gt, ref)
+    _report(f"adjoint {prec_name} {case}", err)
+    assert err <= (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED)
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_adjoint_dot_product(g, ctx, prec_name):
+    """<G m, v> = <m, G^T v> on the GPU operators themselves."""
+    p = workloads.random_case(8, 24, 20, 12, 500, on_top=50)
+    mesh, obs = _dev(g, p)
+    prec = getattr(g, prec_name)
+    d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=prec))
+    gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=prec))
+    lhs, rhs = np.dot(d, p.probe_v), np.dot(p.m, gt)
+    scale = np.linalg.norm(d) * np.linalg.norm(p.probe_v)
+    assert abs(lhs - rhs) <= (1e-12 if prec_name == "GRAV_FP64" else 1e-6) * scale
+
+
+# ------------------------------------------------------------------ data space / trace
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_dataspace_apply_matches_oracle(g, ctx, prec_name):
+    p = workloads.random_case(9, 12, 10, 8, 150, on_top=20, model="blocky")
+    mesh, obs = _dev(g, p)
+    lam = 3.7e-14
+    out = to_np(ctx.dataspace_apply(mesh, obs, _t(p.wdepth), lam, _t(p.probe_v),
+                                    prec=getattr(g, prec_name)))
+    ref = inversion.dataspace_apply(p.mesh, p.obs, p.wdepth, lam, p.probe_v)
+    err = rel_l2(out, ref)
+    _report(f"dataspace {prec_name}", err)
+    assert err <= (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED)
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_trace_and_diagonal(g, ctx, prec_name):
+    import torch
+    p = workloads.random_case(10, 9, 14, 6, 129, on_top=10, on_nodes=10)
+    mesh, obs = _dev(g, p)
+    cov = inversion.covariance_from_weights(p.wdepth)
+    ref_diag = prism.weighted_row_sumsq(p.mesh, p.obs, cov)
+    diag = torch.empty(p.obs.n, dtype=torch.float64, device="cuda")
+    tr = ctx.trace(mesh, obs, _t(p.wdepth), diag=diag, prec=getattr(g, prec_name))
+    tol = 1e-10 if prec_name == "GRAV_FP64" else 1e-5
+    assert rel_l2(to_np(diag), ref_diag) <= tol
+    assert abs(tr - ref_diag.sum()) <= tol * ref_diag.sum()
+
+
+# ------------------------------------------------------------------ inversion
+
+def _config1_reference():
+    p = workloads.config1()
+    G = np.stack([prism.sensitivity_row(p.mesh, p.obs.x[o], p.obs.y[o], p.obs.z[o])
+                  for o in range(p.obs.n)])
+    cov = inversion.covariance_from_weights(p.wdepth)
+    d_clean = G @ p.m
+    d_obs = inversion.add_noise(d_clean, p.noise_draws, p.noise_level)
+    trace = float(np.einsum("ok,k,ok->", G, cov, G))
+    lam = inversion.lambda_rule(trace, p.obs.n)
+    m_chol, _ = inversion.invert_dense(G, cov, lam, d_obs)
+    return p, G, d_obs, trace, lam, m_chol
+
+
+@pytest.fixture(scope="module")
+def config1_ref():
+    return _config1_reference()
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_invert_config1_vs_cholesky(g, ctx, config1_ref, prec_name):
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    m, d_pred, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=p.cg_tol,
+                                 max_iter=2000, want_pred=True, prec=getattr(g, prec_name))
+    print(f"[parity] invert config1 {prec_name}: {info}", flush=True)
+    assert info["converged"] and info["relres"] <= p.cg_tol
+    assert abs(info["trace"] - trace) <= 1e-5 * trace
+    err = rel_l2(to_np(m), m_chol)
+    _report(f"invert config1 {prec_name} density", err)
+    assert err <= 1e-4
+    assert rel_l2(to_np(d_pred), G @ m_chol) <= 1e-4
+
+
+def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, fixed_iters=5)
+    assert info["iters"] == 5 and info["converged"]
+    cov = inversion.covariance_from_weights(p.wdepth)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    y, _, hist = inversion.conjugate_gradient(lambda v: A @ v, d_obs, fixed_iters=5)
+    m_ref5 = cov * (G.T @ y)
+    assert rel_l2(to_np(m), m_ref5) <= 1e-4
+    assert abs(info["relres"] - hist[-1]) <= 1e-3 * hist[-1]
+    m2, _, info2 = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-12, max_iter=3)
+    assert not info2["converged"] and info2["iters"] == 3
+    assert np.all(np.isfinite(to_np(m2)))
+
+
+def test_invert_with_reference_model(g, ctx):
+    p = workloads.random_case(11, 6, 5, 4, 40, model="blocky")
+    G = np.stack([prism.sensitivity_row(p.mesh, p.obs.x[o], p.obs.y[o], p.obs.z[o])
+                  for o in range(p.obs.n)])
+    cov = inversion.covariance_from_weights(p.wdepth)
+    d_obs = inversion.add_noise(G @ p.m, p.noise_draws, 0.01)
+    m_ref = np.full(p.mesh.ncells, 0.1)
+    lam = 1e-2 * float(np.einsum("ok,k,ok->", G, cov, G)) / p.obs.n
+    m_chol, _ = inversion.invert_dense(G, cov, lam, d_obs, m_ref)
+    mesh, obs = _dev(g, p)
+    m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, m_ref=_t(m_ref),
+                            tol=1e-10, max_iter=500, prec=g.GRAV_FP64)
+    assert rel_l2(to_np(m), m_chol) <= 1e-6
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def test_config2_forward_adjoint_sampled(g, ctx):
+    p = workloads.config2()
+    gold = np.load(os.path.join(HERE, "golden", "config2_rows.npz"))
+    mesh, obs = _dev(g, p)
+    for prec_name, tol in (("GRAV_MIXED", TOL_MIXED), ("GRAV_FP64", TOL_F64)):
+        prec = getattr(g, prec_name)
+        d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=prec))
+        err = rel_l2(d[gold["rows"]], gold["d"])
+        _report(f"config2 forward {prec_name} (256 rows)", err)
+        assert err <= tol
+        gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=prec))
+        err = rel_l2(gt[gold["cells"]], gold["gtv"])
+        _report(f"config2 adjoint {prec_name} (64 cells)", err)
+        assert err <= (tol if prec_name == "GRAV_FP64" else 1e-5)
+
+
+def test_config4_forward_sampled_rows(g, ctx):
+    """Paper-scale G m (178,797 x 3,307,500) in the launch configuration the
+    benchmark times, checked on 2,000 seeded rows computed by the oracle."""
+    p = workloads.config4()
+    gold = np.load(os.path.join(HERE, "golden", "config4_rows.npz"))
+    mesh, obs = _dev(g, p)
+    d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=g.GRAV_MIXED))
+    err = rel_l2(d[gold["rows"]], gold["d"])
+    _report("config4 forward GRAV_MIXED (2000 rows)", err)
+    assert err <= TOL_MIXED
+    gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=g.GRAV_MIXED))
+    err = rel_l2(gt[gold["cells"]], gold["gtv"])
+    _report("config4 adjoint GRAV_MIXED (48 cells)", err)
+    assert err <= TOL_MIXED
+
+
+# ------------------------------------------------------------------ determinism and errors
+
+def test_bitwise_repeatable(g, ctx):
+    p = workloads.random_case(12, 20, 20, 10, 300)
+    mesh, obs = _dev(g, p)
+    for prec in (g.GRAV_MIXED, g.GRAV_FP64):
+        a = to_np(ctx.forward(mesh, obs, _t(p.m), prec=prec))
+        b = to_np(ctx.forward(mesh, obs, _t(p.m), prec=prec))
+        assert np.array_equal(a, b)
+        a = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=prec))
+        b = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=prec))
+        assert np.array_equal(a, b)
+
+
+def test_error_paths(g, ctx):
+    import torch
+    p = workloads.random_case(13, 4, 4, 3, 10)
+    mesh, obs = _dev(g, p)
+    m = _t(p.m)
+    # observation below the mesh top
+    bad = g.DeviceObs(p.obs.x, p.obs.y, p.obs.z + 1e3)
+    with pytest.raises(g.GravError) as e:
+        ctx.forward(mesh, bad, m)
+    assert e.value.code == g.GRAV_EINVAL and "below" in str(e.value)
+    # non-increasing nodes
+    xn = p.mesh.xn.copy()
+    xn[2] = xn[1]
+    badmesh = g.DeviceMesh(xn, p.mesh.yn, p.mesh.zn)
+    with pytest.raises(g.GravError) as e:
+        ctx.forward(badmesh, obs, m)
+    assert e.value.code == g.GRAV_EINVAL
+    # non-positive depth weight
+    w = p.wdepth.copy()
+    w[3] = 0.0
+    with pytest.raises(g.GravError) as e:
+        ctx.dataspace_apply(mesh, obs, _t(w), 1.0, _t(p.probe_v))
+    assert e.value.code == g.GRAV_EINVAL
+    # negative lambda for the operator
+    with pytest.raises(g.GravError):
+        ctx.dataspace_apply(mesh, obs, _t(p.wdepth), -1.0, _t(p.probe_v))
+    # NULL pointers straight through the C ABI
+    import ctypes
+    rc = g.lib.grav_forward(ctx.handle, ctypes.byref(mesh.c), ctypes.byref(obs.c), None, None,
+                            g.GRAV_MIXED, None)
+    assert rc == g.GRAV_EINVAL
+    # workspace too small
+    small = g.Context(device=0, workspace_bytes=4096)
+    with pytest.raises(g.GravError) as e:
+        small.forward(mesh, obs, m)
+    assert e.value.code == g.GRAV_ENOMEM
+    small.close()
+    # unsupported precision for the operator
+    with pytest.raises(g.GravError):
+        ctx.forward(mesh, obs, m, prec=g.GRAV_MIXED_BF16X3)
+    torch.cuda.synchronize()
