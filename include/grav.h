@@ -194,6 +194,19 @@ int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs
                        const float *models, int32_t K, float *D, grav_prec prec,
                        grav_stream stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics: per-kernel timing.  With timing enabled, the library records a
+ * pair of HIP events on the call's stream around every launch of its sweep
+ * kernels ("forward_mixed", "forward_f64", "adjoint_mixed", "adjoint_f64",
+ * "trace_mixed", "trace_f64", "multi_bf16x3", "multi_fp32").
+ * grav_kernel_time() waits for the recorded events of `kernel` and returns the
+ * summed duration (HOST *total_ms) and launch count (HOST *launches) since the
+ * last reset.  Errors: GRAV_EINVAL (null ctx/out, unknown kernel name). */
+int grav_set_timing(grav_ctx *ctx, int32_t enable);
+int grav_kernel_time(grav_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+int grav_reset_timing(grav_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,10 @@ class GravError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Importing it
+    # first makes libgrav.so bind to that same runtime, so device pointers and
+    # streams from torch are valid in the library (one runtime per process).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2602_03857_amd.build` "
@@ -69,6 +73,9 @@ def _load():
                                        P(CgInfo), ctypes.c_int, vp]),
         "grav_forward_multi": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, i32, vp, ctypes.c_int,
                                               vp]),
+        "grav_set_timing": (ctypes.c_int, [vp, i32]),
+        "grav_kernel_time": (ctypes.c_int, [vp, ctypes.c_char_p, P(dbl), P(i64)]),
+        "grav_reset_timing": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -82,5 +89,6 @@ lib = _load()
 EXPORTED = [
     "grav_ctx_opts_default", "grav_ctx_create", "grav_ctx_destroy", "grav_last_error",
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
-    "grav_invert", "grav_forward_multi",
+    "grav_invert", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
+    "grav_reset_timing",
 ]

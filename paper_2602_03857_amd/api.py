@@ -130,6 +130,20 @@ class Context:
             stream = torch.cuda.current_stream(self.device)
         return ctypes.c_void_p(stream.cuda_stream)
 
+    # ------------------------------------------------------------ diagnostics
+    def set_timing(self, enable: bool = True) -> None:
+        self._rc(lib.grav_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_time(self, kernel: str):
+        """(total_ms, launches) of a sweep kernel since the last reset (HIP events)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._rc(lib.grav_kernel_time(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def reset_timing(self) -> None:
+        self._rc(lib.grav_reset_timing(self._h))
+
     # ------------------------------------------------------------ operators
     def forward(self, mesh: DeviceMesh, obs: DeviceObs, m, d=None, prec=GRAV_MIXED, stream=None):
         """d = G m.  m: (M,) float64 device tensor."""

@@ -15,6 +15,7 @@
 using namespace grav;
 
 static thread_local std::string g_create_error;
+extern "C" int grav_reset_timing(grav_ctx *ctx);
 
 // ---------------------------------------------------------------- helpers
 
@@ -103,11 +104,13 @@ int op_forward(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const doub
         if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the forward sweep");
         HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
         HIP_TRY(launch_edge_weights(g, m, w2, st), "edge weights");
+        KernelTimer kt(ctx, "forward_mixed", st);
         HIP_TRY(launch_forward_mixed(g, o, hk, w2, fp, part, st), "forward sweep");
     } else {
         double *wn = ar.take<double>(g.nnodes());
         if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the forward sweep");
         HIP_TRY(launch_node_weights(g, m, wn, st), "node weights");
+        KernelTimer kt(ctx, "forward_f64", st);
         HIP_TRY(launch_forward_f64(g, o, wn, fp, part, st), "forward sweep");
     }
     HIP_TRY(launch_reduce_parts(part, fp.nchunk, o.n, scale, add, coef, d, st), "forward reduce");
@@ -127,7 +130,10 @@ int op_adjoint(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const doub
         double *U = ar.take<double>(g.nsegs());
         if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the adjoint sweep");
         HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
-        HIP_TRY(launch_adjoint_mixed(g, o, hk, v, ap, upart, st), "adjoint sweep");
+        {
+            KernelTimer kt(ctx, "adjoint_mixed", st);
+            HIP_TRY(launch_adjoint_mixed(g, o, hk, v, ap, upart, st), "adjoint sweep");
+        }
         HIP_TRY(launch_reduce_parts(upart, ap.nparts, g.nsegs(), 1.0, nullptr, 0.0, U, st),
                 "adjoint reduce");
         HIP_TRY(launch_adjoint_finish_edges(g, U, scale, wdepth, base, out, st), "adjoint finish");
@@ -136,7 +142,10 @@ int op_adjoint(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const doub
         double *ppart = ar.take<double>((size_t)ap.nparts * g.nnodes());
         double *P = ar.take<double>(g.nnodes());
         if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the adjoint sweep");
-        HIP_TRY(launch_adjoint_f64(g, o, v, ap, ppart, st), "adjoint sweep");
+        {
+            KernelTimer kt(ctx, "adjoint_f64", st);
+            HIP_TRY(launch_adjoint_f64(g, o, v, ap, ppart, st), "adjoint sweep");
+        }
         HIP_TRY(launch_reduce_parts(ppart, ap.nparts, g.nnodes(), 1.0, nullptr, 0.0, P, st),
                 "adjoint reduce");
         HIP_TRY(launch_adjoint_finish_nodes(g, P, scale, wdepth, base, out, st), "adjoint finish");
@@ -170,8 +179,10 @@ int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double
     if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the trace sweep");
     if (prec == GRAV_MIXED) {
         HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
+        KernelTimer kt(ctx, "trace_mixed", st);
         HIP_TRY(launch_trace_mixed(g, o, hk, wdepth, tp, part, st), "trace sweep");
     } else {
+        KernelTimer kt(ctx, "trace_f64", st);
         HIP_TRY(launch_trace_f64(g, o, wdepth, tp, part, st), "trace sweep");
     }
     HIP_TRY(launch_reduce_parts(part, tp.nchunk, o.n, GRAV_GAMMA * GRAV_GAMMA, nullptr, 0.0, dg, st),
@@ -248,6 +259,7 @@ extern "C" void grav_ctx_destroy(grav_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    (void)grav_reset_timing(ctx);
     (void)hipFree(ctx->ws);
     (void)hipHostFree(ctx->h_pinned);
     delete ctx;
@@ -367,4 +379,84 @@ extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs 
                              ArrayCheck{m_ref, g.ncells(), false}});
     if (rc) return rc;
     return grav::run_invert(ctx, g, o, d_obs, wdepth, lambda, m_ref, *cg, m_out, d_pred, info, prec, st);
+}
+
+// ---------------------------------------------------------------- timing
+
+static const char *const kTimedKernels[] = {"forward_mixed", "forward_f64", "adjoint_mixed",
+                                            "adjoint_f64", "trace_mixed", "trace_f64",
+                                            "multi_bf16x3", "multi_fp32"};
+
+namespace grav {
+
+KernelTimer::KernelTimer(grav_ctx *ctx, const char *name, hipStream_t st)
+    : ctx_(ctx), name_(name), st_(st) {
+    if (!ctx_->timing) return;
+    if (hipEventCreate(&start_) != hipSuccess) { start_ = nullptr; return; }
+    if (hipEventRecord(start_, st_) != hipSuccess) {
+        (void)hipEventDestroy(start_);
+        start_ = nullptr;
+    }
+}
+
+KernelTimer::~KernelTimer() {
+    if (!start_) return;
+    hipEvent_t stop = nullptr;
+    if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, st_) != hipSuccess) {
+        (void)hipEventDestroy(start_);
+        if (stop) (void)hipEventDestroy(stop);
+        return;
+    }
+    ctx_->pending[name_].emplace_back(start_, stop);
+}
+
+}  // namespace grav
+
+static bool known_kernel(const char *k) {
+    for (const char *n : kTimedKernels)
+        if (std::strcmp(n, k) == 0) return true;
+    return false;
+}
+
+extern "C" int grav_set_timing(grav_ctx *ctx, int32_t enable) {
+    if (!ctx) return GRAV_EINVAL;
+    ctx->timing = enable != 0;
+    return GRAV_OK;
+}
+
+extern "C" int grav_kernel_time(grav_ctx *ctx, const char *kernel, double *total_ms,
+                                int64_t *launches) {
+    if (!ctx || !kernel || !total_ms || !launches) return GRAV_EINVAL;
+    if (!known_kernel(kernel)) return fail(ctx, GRAV_EINVAL, "unknown kernel name");
+    auto &tot = ctx->totals[kernel];
+    auto it = ctx->pending.find(kernel);
+    if (it != ctx->pending.end()) {
+        for (auto &ev : it->second) {
+            hipError_t e = hipEventSynchronize(ev.second);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+            if (e != hipSuccess) return hip_fail(ctx, e, "kernel timing");
+            tot.first += ms;
+            tot.second += 1;
+        }
+        it->second.clear();
+    }
+    *total_ms = tot.first;
+    *launches = tot.second;
+    return GRAV_OK;
+}
+
+extern "C" int grav_reset_timing(grav_ctx *ctx) {
+    if (!ctx) return GRAV_EINVAL;
+    for (auto &kv : ctx->pending)
+        for (auto &ev : kv.second) {
+            (void)hipEventSynchronize(ev.second);
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    ctx->pending.clear();
+    ctx->totals.clear();
+    return GRAV_OK;
 }

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <initializer_list>
+#include <map>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "grav_internal.h"
 
@@ -17,6 +20,9 @@ struct grav_ctx {
     int *h_flags = nullptr;
     double *h_scal = nullptr;
     std::string err;
+    bool timing = false;    // record events around sweep launches
+    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::map<std::string, std::pair<double, int64_t>> totals;
 };
 
 namespace grav {
@@ -53,6 +59,19 @@ int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double
 int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
                const double *wdepth, double lambda, const double *m_ref, const grav_cg_opts &cg,
                double *m_out, double *d_pred, grav_cg_info *info, grav_prec prec, hipStream_t st);
+
+// Records a start event now and an end event when it goes out of scope (both
+// on `st`), if timing is enabled on the context.
+class KernelTimer {
+  public:
+    KernelTimer(grav_ctx *ctx, const char *name, hipStream_t st);
+    ~KernelTimer();
+  private:
+    grav_ctx *ctx_;
+    const char *name_;
+    hipStream_t st_;
+    hipEvent_t start_ = nullptr;
+};
 
 uint64_t workspace_need(int nx, int ny, int nz, int64_t n, grav_op op, grav_prec prec, int K);
 uint64_t multi_workspace_need(const Mesh &g, int64_t n, grav_prec prec, int K);

@@ -23,12 +23,78 @@
 // Singular limits, taken by select (never by multiplying by zero, so that an
 // infinite or NaN intermediate of a discarded branch cannot leak):
 // x = 0 => the x*ln term is 0; y = 0 => the y*ln term is 0; z1 = 0 => the
-// z1*atan term is 0.  These are the continuous limits of Eq. 2.
+// z1*atan term is 0.  These are the continuous limits of Eq. 2.  In FP32 a
+// horizontal offset below kTinyOffset (0.1 mm) is treated as 0, so that its
+// square cannot underflow into a zero denominator; the term it drops is
+// bounded by |x| * |ln(...)|, below 3e-3 m * (kg/m^3 weight) per segment.
+//
+// Elementary functions of the FP32 path (all in this file, no library calls):
+//  * reciprocal, square root, log2: the gfx950 hardware instructions
+//    (v_rcp_f32, v_sqrt_f32, v_log_f32).
+//  * log1p(t), t >= 0: u = 1 + t rounded, c = t - (u - 1) its exact rounding
+//    error (Sterbenz), log1p(t) = ln(u) + c/u; c/u is replaced by
+//    c * max(0, 2 - u), which differs from it by less than 0.5 c for u <= 2
+//    and drops it above 2 where c/u < 2^-24 relative to ln(u) >= ln 2.
+//  * atan(n/d), d >= 0: r = min(|n|, d) / max(|n|, d) in [0, 1],
+//    atan(r) = r P(r^2) with a degree-8 polynomial in r^2 fitted to the
+//    relative error of atan on [0, 1] by iteratively reweighted least squares
+//    (max relative error 1.4e-7 in FP32), then pi/2 - atan(r) if |n| > d, and
+//    the sign of n.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace grav {
+
+namespace fm {
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
+
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kHalfPi = 1.57079632679489662f;
+
+// atan(r) = r * P(r^2) on [0, 1]
+constexpr float kAt0 = 1.0f;
+constexpr float kAt1 = -0.3333307206630707f;
+constexpr float kAt2 = 0.1999262124300003f;
+constexpr float kAt3 = -0.142036572098732f;
+constexpr float kAt4 = 0.10640984773635864f;
+constexpr float kAt5 = -0.07504411041736603f;
+constexpr float kAt6 = 0.042692989110946655f;
+constexpr float kAt7 = -0.01606959104537964f;
+constexpr float kAt8 = 0.002850143937394023f;
+
+// atan(n / d) for d >= 0 (n = d = 0 gives NaN; callers discard it).
+__device__ __forceinline__ float atan_ratio(float n, float d) {
+    const float a = fabsf(n);
+    const float r = fminf(a, d) * rcp(fmaxf(a, d));
+    const float r2 = r * r;
+    float p = fmaf(kAt8, r2, kAt7);
+    p = fmaf(p, r2, kAt6);
+    p = fmaf(p, r2, kAt5);
+    p = fmaf(p, r2, kAt4);
+    p = fmaf(p, r2, kAt3);
+    p = fmaf(p, r2, kAt2);
+    p = fmaf(p, r2, kAt1);
+    p = fmaf(p, r2, kAt0);
+    p *= r;
+    p = (a > d) ? (kHalfPi - p) : p;
+    return copysignf(p, n);
+}
+
+// log1p(t) for t >= 0.
+__device__ __forceinline__ float log1p_pos(float t) {
+    const float u = 1.0f + t;
+    const float c = t - (u - 1.0f);
+    const float w = fmaxf(2.0f - u, 0.0f);
+    return fmaf(log2(u), kLn2, c * w);
+}
+
+}  // namespace fm
+
+constexpr float kTinyOffset = 1.0e-4f;   // metres
 
 // Per (observation, mesh column) quantities, FP32, from FP64 differences.
 struct Column {
@@ -36,53 +102,78 @@ struct Column {
     float xx, yy;    // x^2, y^2
     float s;         // x^2 + y^2
     float xy;        // x*y
-    bool xnz, ynz;   // x != 0, y != 0
+    float xy2;       // (x*y)^2
+    bool xnz, ynz;   // |x|, |y| above kTinyOffset
     bool xneg, yneg; // x < 0, y < 0
 };
 
-__device__ __forceinline__ Column make_column(double X, double Y, double xo, double yo) {
+// Column terms from FP32 offsets (x, y) already reduced by column_offset().
+__device__ __forceinline__ Column column_from_xy(float x, float y) {
     Column c;
-    c.x = static_cast<float>(X - xo);
-    c.y = static_cast<float>(Y - yo);
+    c.x = x;
+    c.y = y;
+    c.xnz = x != 0.0f;
+    c.ynz = y != 0.0f;
     c.xx = c.x * c.x;
     c.yy = c.y * c.y;
     c.s = c.xx + c.yy;
     c.xy = c.x * c.y;
-    c.xnz = c.x != 0.0f;
-    c.ynz = c.y != 0.0f;
+    c.xy2 = c.xy * c.xy;
     c.xneg = c.x < 0.0f;
     c.yneg = c.y < 0.0f;
     return c;
 }
 
-__device__ __forceinline__ float node_radius(const Column &c, float z) {
-    return sqrtf(fmaf(z, z, c.s));
+// FP64 coordinate difference rounded to FP32, offsets below kTinyOffset -> 0.
+__device__ __forceinline__ float column_offset(double X, double xo) {
+    const float x = static_cast<float>(X - xo);
+    return fabsf(x) > kTinyOffset ? x : 0.0f;
 }
 
-// S = Psi(x, y, z2) - Psi(x, y, z1) for one vertical edge segment, z2 = z1 + h,
-// z1 >= 0, R1 = |(x, y, z1)|, R2 = |(x, y, z2)|.
-__device__ __forceinline__ float edge_segment(const Column &c, float z1, float z2, float h,
-                                              float R1, float R2) {
-    const float hz = h * (z1 + z2);
-    const float dR = hz / (R1 + R2);                 // R2 - R1
-    const float z1s = z1 * z1;
-    // ln(R2 + y) - ln(R1 + y) = log1p(dR / (R1 + y))
-    const float denY = c.yneg ? (c.xx + z1s) : (R1 + c.y);
-    const float numY = c.yneg ? (R1 - c.y) : 1.0f;
-    const float lnY = log1pf(dR * numY / denY);
-    // ln(R2 + x) - ln(R1 + x)
-    const float denX = c.xneg ? (c.yy + z1s) : (R1 + c.x);
-    const float numX = c.xneg ? (R1 - c.x) : 1.0f;
-    const float lnX = log1pf(dR * numX / denX);
+__device__ __forceinline__ Column make_column(double X, double Y, double xo, double yo) {
+    return column_from_xy(column_offset(X, xo), column_offset(Y, yo));
+}
+
+// Per (observation, mesh node) quantities along a column: depth below the
+// observation z >= 0, z^2, distance R and z*R.  The bottom node of one
+// segment is the top node of the next.
+struct Node {
+    float z, zz, R, zR;
+};
+
+__device__ __forceinline__ Node make_node(const Column &c, float z) {
+    Node n;
+    n.z = z;
+    n.zz = z * z;
+    n.R = fm::sqrt(c.s + n.zz);
+    n.zR = z * n.R;
+    return n;
+}
+
+// S = Psi(x, y, z2) - Psi(x, y, z1) for one vertical edge segment between
+// node t (top, depth z1 >= 0) and node b (bottom, z2 = z1 + h).
+__device__ __forceinline__ float edge_segment(const Column &c, const Node &t, const Node &b,
+                                              float h) {
+    const float hz = h * (t.z + b.z);
+    // R1 + y (rationalised for y < 0) and R1 + x; a denominator belonging to a
+    // discarded log term (x = 0, resp. y = 0) is replaced by 1.
+    float denY = c.yneg ? (c.xx + t.zz) : (t.R + c.y);
+    float denX = c.xneg ? (c.yy + t.zz) : (t.R + c.x);
+    denY = c.xnz ? denY : 1.0f;
+    denX = c.ynz ? denX : 1.0f;
+    const float numY = c.yneg ? (t.R - c.y) : 1.0f;
+    const float numX = c.xneg ? (t.R - c.x) : 1.0f;
+    // dR/(R1 + y) and dR/(R1 + x) with dR = hz / (R1 + R2), one reciprocal
+    const float q = hz * fm::rcp((t.R + b.R) * (denY * denX));
+    const float lnY = fm::log1p_pos(q * numY * denX);   // ln(R2 + y) - ln(R1 + y)
+    const float lnX = fm::log1p_pos(q * numX * denY);   // ln(R2 + x) - ln(R1 + x)
     // z2 atan(u2) - z1 atan(u1) = h atan(u2) + z1 atan(delta)
-    const float zR1 = z1 * R1;
-    const float zR2 = z2 * R2;
-    const float at2 = atanf(c.xy / zR2);
-    const float num = -c.xy * hz * (c.s + z1s + z2 * z2);
-    const float den = (zR1 + zR2) * fmaf(zR1, zR2, c.xy * c.xy);
-    const float atd = atanf(num / den);
+    const float at2 = fm::atan_ratio(c.xy, b.zR);
+    const float num = -c.xy * hz * (c.s + t.zz + b.zz);
+    const float den = (t.zR + b.zR) * fmaf(t.zR, b.zR, c.xy2);
+    const float atd = fm::atan_ratio(num, den);
     float S = h * at2;
-    S = (z1 > 0.0f) ? fmaf(z1, atd, S) : S;
+    S = (t.z > 0.0f) ? fmaf(t.z, atd, S) : S;
     S = c.xnz ? fmaf(-c.x, lnY, S) : S;
     S = c.ynz ? fmaf(-c.y, lnX, S) : S;
     return S;

@@ -1,17 +1,362 @@
-// Multi-model forward (placeholder until the MFMA path lands).
+// Multi-model forward D = G [m_1 ... m_K] (paper Eq. 6 applied to a block of
+// K <= 64 density models): a dense contraction over prisms, so it runs on
+// the matrix cores.
+//
+// Per workgroup: 64 observations x all 64 (padded) models, looping over
+// 4 x 4 blocks of prism columns and, inside each, over the layers.  One layer
+// step of one block:
+//   1. VALU: edge-segment terms S for the 5 x 5 vertical edges around the 16
+//      prisms, for the 64 observations (z-carry of R along each edge) -> LDS.
+//      25 edge terms serve 16 prisms (1.56 per prism).
+//   2. VALU: per prism G = S00 - S10 - S01 + S11 (the (x, y) vertex parity of
+//      Eq. 1), split into bf16 hi = bf16(G), lo = bf16(G - hi) -> LDS in the
+//      MFMA A-operand order (obs x 16 prisms).
+//   3. MFMA: four waves each own a 32 obs x 32 model block;
+//      acc += A_hi B_hi + A_hi B_lo + A_lo B_hi with v_mfma_f32_32x32x16_bf16
+//      (FP32 accumulation), B = the models pre-split into bf16 hi/lo and
+//      packed so that each lane loads its 8 operands with one 16-byte load.
+// After each prism-column block the FP32 MFMA accumulators are added into
+// FP64 registers, so FP32 accumulates at most 16 nz terms.  The GRAV_FP32_VALU
+// variant keeps steps 1-2 (G in FP32) and contracts on the vector ALUs.
+#include <hip/hip_runtime.h>
+
 #include "api_internal.h"
+#include "edge_math.h"
 
 namespace grav {
-uint64_t multi_workspace_need(const Mesh &g, int64_t n, grav_prec prec, int K) {
-    (void)g; (void)n; (void)prec; (void)K;
-    return 0;
+
+namespace {
+
+constexpr int kTileObs = 64;
+constexpr int kPB = 4;                                   // prism columns per block side
+constexpr int kEdgeSide = kPB + 1;
+constexpr int kEdgeCols = kEdgeSide * kEdgeSide;         // 25 edge columns per block
+constexpr int kColsPerWave = (kEdgeCols + 3) / 4;        // 7 (wave w takes w, w+4, ...)
+constexpr int kPrismsPerStep = kPB * kPB;                // 16 = MFMA K
+constexpr int kModels = 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Packed bf16 hi/lo models: index ((blk * nz + k) * 64 + j) * 16 + p, with
+// blk = bi * nby + bj the 4x4 prism-column block and p = ii * 4 + jj inside it.
+__global__ void k_pack_models_bf16(const float *__restrict__ models, int K, int nx, int ny, int nz,
+                                   int nby, int64_t total, __bf16 *__restrict__ hi,
+                                   __bf16 *__restrict__ lo) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(idx & 15);
+        const int j = (int)((idx >> 4) & 63);
+        const int64_t rest = idx >> 10;
+        const int k = (int)(rest % nz);
+        const int64_t blk = rest / nz;
+        const int i = (int)(blk / nby) * kPB + p / kPB;
+        const int jj = (int)(blk % nby) * kPB + p % kPB;
+        float v = 0.0f;
+        if (j < K && i < nx && jj < ny) v = models[(((int64_t)i * ny + jj) * nz + k) * K + j];
+        const __bf16 h = static_cast<__bf16>(v);
+        hi[idx] = h;
+        lo[idx] = static_cast<__bf16>(v - static_cast<float>(h));
+    }
 }
+
+// Packed FP32 models for the VALU path: ((blk * nz + k) * 16 + p) * 64 + j.
+__global__ void k_pack_models_f32(const float *__restrict__ models, int K, int nx, int ny, int nz,
+                                  int nby, int64_t total, float *__restrict__ out) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx & 63);
+        const int p = (int)((idx >> 6) & 15);
+        const int64_t rest = idx >> 10;
+        const int k = (int)(rest % nz);
+        const int64_t blk = rest / nz;
+        const int i = (int)(blk / nby) * kPB + p / kPB;
+        const int jj = (int)(blk % nby) * kPB + p % kPB;
+        float v = 0.0f;
+        if (j < K && i < nx && jj < ny) v = models[(((int64_t)i * ny + jj) * nz + k) * K + j];
+        out[idx] = v;
+    }
+}
+
+template <bool kMfma>
+__global__ __launch_bounds__(256) void k_forward_multi(
+    const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
+    int nx, int ny, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
+    const double *__restrict__ oy, const double *__restrict__ oz, int64_t n,
+    const __bf16 *__restrict__ bhi, const __bf16 *__restrict__ blo,
+    const float *__restrict__ b32, int nby, int64_t nblk, int64_t blocks_per_chunk, int nchunk,
+    double *__restrict__ partial) {
+    __shared__ float sS[kEdgeCols][kTileObs];
+    __shared__ __attribute__((aligned(16))) __bf16 sAhi[kTileObs][kPrismsPerStep];
+    __shared__ __attribute__((aligned(16))) __bf16 sAlo[kTileObs][kPrismsPerStep];
+    __shared__ __attribute__((aligned(16))) float sA32[kTileObs][kPrismsPerStep];
+    __shared__ __attribute__((aligned(16))) float sB32[kPrismsPerStep][kModels];
+
+    const int chunk = (int)(blockIdx.x % nchunk);
+    const int64_t tile = blockIdx.x / nchunk;
+    const int t = threadIdx.x;
+    const int lo_ = t & 63;          // observation within the tile (phases 1-2), lane (phase 3)
+    const int wv = t >> 6;           // wave index 0..3
+    const int64_t o = tile * kTileObs + lo_;
+    const int64_t oc = o < n ? o : n - 1;
+    const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
+    const float ztop = static_cast<float>(zn[0] - zo);
+    const int64_t b0 = (int64_t)chunk * blocks_per_chunk;
+    const int64_t b1 = b0 + blocks_per_chunk < nblk ? b0 + blocks_per_chunk : nblk;
+
+    // phase-3 roles
+    const int r0 = 32 * (wv & 1), c0 = 32 * (wv >> 1);
+    f32x16 acc;
+    float acc32[16];
+    double acc64[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        acc[v] = 0.0f;
+        acc32[v] = 0.0f;
+        acc64[v] = 0.0;
+    }
+
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        const int i0 = (int)(blk / nby) * kPB;
+        const int j0 = (int)(blk % nby) * kPB;
+        float cx[kColsPerWave], cy[kColsPerWave], cR[kColsPerWave], czR[kColsPerWave];
+        bool valid[kColsPerWave];
+#pragma unroll
+        for (int u = 0; u < kColsPerWave; ++u) {
+            const int c = wv + 4 * u;
+            const int a = i0 + c / kEdgeSide, b = j0 + c % kEdgeSide;
+            valid[u] = c < kEdgeCols && a <= nx && b <= ny;
+            const int ac = a <= nx ? a : nx, bc = b <= ny ? b : ny;
+            cx[u] = column_offset(xn[ac], xo);
+            cy[u] = column_offset(yn[bc], yo);
+            const Column col = column_from_xy(cx[u], cy[u]);
+            const Node top = make_node(col, ztop);
+            cR[u] = top.R;
+            czR[u] = top.zR;
+        }
+        float zt = ztop, zzt = ztop * ztop;
+        for (int k = 0; k < nz; ++k) {
+            const float zb = static_cast<float>(zn[k + 1] - zo);
+            const float h = hk[k];
+            // phase 1: edge terms of this layer
+#pragma unroll
+            for (int u = 0; u < kColsPerWave; ++u) {
+                const int c = wv + 4 * u;
+                if (c < kEdgeCols) {
+                    const Column col = column_from_xy(cx[u], cy[u]);
+                    Node top;
+                    top.z = zt;
+                    top.zz = zzt;
+                    top.R = cR[u];
+                    top.zR = czR[u];
+                    const Node bot = make_node(col, zb);
+                    const float S = edge_segment(col, top, bot, h);
+                    sS[c][lo_] = valid[u] ? S : 0.0f;
+                    cR[u] = bot.R;
+                    czR[u] = bot.zR;
+                }
+            }
+            zt = zb;
+            zzt = zb * zb;
+            __syncthreads();
+            // phase 2: prism terms of prisms (ii = wv, jj = 0..3) for observation lo_
+#pragma unroll
+            for (int q = 0; q < kPB; ++q) {
+                const int e = wv * kEdgeSide + q;
+                float G = (sS[e][lo_] - sS[e + kEdgeSide][lo_]) - (sS[e + 1][lo_] - sS[e + kEdgeSide + 1][lo_]);
+                G = (i0 + wv < nx && j0 + q < ny) ? G : 0.0f;
+                const int p = wv * kPB + q;
+                if (kMfma) {
+                    const __bf16 h16 = static_cast<__bf16>(G);
+                    sAhi[lo_][p] = h16;
+                    sAlo[lo_][p] = static_cast<__bf16>(G - static_cast<float>(h16));
+                } else {
+                    sA32[lo_][p] = G;
+                }
+            }
+            if (!kMfma) {
+                const float4 *src = reinterpret_cast<const float4 *>(
+                    b32 + ((blk * nz + k) * kPrismsPerStep) * kModels);
+                reinterpret_cast<float4 *>(&sB32[0][0])[t] = src[t];
+            }
+            __syncthreads();
+            // phase 3: contraction over the 16 prisms of this step
+            if (kMfma) {
+                const int l = lo_;
+                const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(&sAhi[r0 + (l & 31)][(l >> 5) * 8]);
+                const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(&sAlo[r0 + (l & 31)][(l >> 5) * 8]);
+                const int64_t bo = ((blk * nz + k) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(bhi + bo);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(blo + bo);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bh, acc, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int p = 0; p < kPrismsPerStep; ++p) {
+                    const float gp = sA32[lo_][p];
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) acc32[v] = fmaf(gp, sB32[p][wv * 16 + v], acc32[v]);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            if (kMfma) {
+                acc64[v] += static_cast<double>(acc[v]);
+                acc[v] = 0.0f;
+            } else {
+                acc64[v] += static_cast<double>(acc32[v]);
+                acc32[v] = 0.0f;
+            }
+        }
+    }
+
+    if (kMfma) {
+        const int l = lo_;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = r0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+            const int64_t og = tile * kTileObs + row;
+            if (og < n) partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] = acc64[v];
+        }
+    } else if (o < n) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = acc64[v];
+    }
+}
+
+// D[o*K + j] = gamma * sum_chunks partial[chunk][o][j]   (j < K), FP32 output
+__global__ void k_reduce_multi(const double *__restrict__ partial, int nchunk, int64_t n, int K,
+                               double scale, float *__restrict__ D) {
+    const int64_t total = n * K;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = idx / K;
+        const int j = (int)(idx % K);
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += partial[((int64_t)c * n + o) * kModels + j];
+        D[idx] = static_cast<float>(scale * s);
+    }
+}
+
+__global__ void k_layer_thickness_m(const double *__restrict__ zn, int nz, float *__restrict__ hk) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nz) hk[k] = static_cast<float>(zn[k + 1] - zn[k]);
+}
+
+struct MultiPlan {
+    int nbx, nby;
+    int64_t nblk, ntile, blocks_per_chunk;
+    int nchunk;
+};
+
+MultiPlan plan_multi(const Mesh &g, int64_t n) {
+    MultiPlan p;
+    p.nbx = (int)cdiv(g.nx, kPB);
+    p.nby = (int)cdiv(g.ny, kPB);
+    p.nblk = (int64_t)p.nbx * p.nby;
+    p.ntile = cdiv(n, kTileObs);
+    int64_t nchunk = cdiv(4096, p.ntile);
+    if (nchunk > p.nblk) nchunk = p.nblk;
+    if (nchunk < 1) nchunk = 1;
+    p.blocks_per_chunk = cdiv(p.nblk, nchunk);
+    p.nchunk = (int)cdiv(p.nblk, p.blocks_per_chunk);
+    return p;
+}
+
+unsigned grid_cap(int64_t len) {
+    int64_t gsz = cdiv(len, 256);
+    if (gsz < 1) gsz = 1;
+    if (gsz > 16384) gsz = 16384;
+    return (unsigned)gsz;
+}
+
+}  // namespace
+
+uint64_t multi_workspace_need(const Mesh &g, int64_t n, grav_prec prec, int K) {
+    (void)K;
+    const MultiPlan mp = plan_multi(g, n);
+    Counter c;
+    const size_t packed = (size_t)mp.nblk * g.nz * kModels * kPrismsPerStep;
+    if (prec == GRAV_MIXED_BF16X3) {
+        c.take<__bf16>(packed);
+        c.take<__bf16>(packed);
+    } else {
+        c.take<float>(packed);
+    }
+    c.take<float>(g.nz);
+    c.take<double>((size_t)mp.nchunk * n * kModels);
+    return c.off;
+}
+
 }  // namespace grav
+
+using namespace grav;
 
 extern "C" int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
                                   const float *models, int32_t K, float *D, grav_prec prec,
                                   grav_stream stream) {
-    (void)mesh; (void)obs; (void)models; (void)K; (void)D; (void)prec; (void)stream;
     if (!ctx) return GRAV_EINVAL;
-    return grav::fail(ctx, GRAV_EINVAL, "multi-model forward not available");
+    ctx->err.clear();
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!models || !D) return fail(ctx, GRAV_EINVAL, "models or D is NULL");
+    if (K < 1 || K > kModels) return fail(ctx, GRAV_EINVAL, "K must be in [1, 64]");
+    if (prec != GRAV_MIXED_BF16X3 && prec != GRAV_FP32_VALU)
+        return fail(ctx, GRAV_EINVAL, "precision must be GRAV_MIXED_BF16X3 or GRAV_FP32_VALU");
+    const Mesh g{mesh->nx, mesh->ny, mesh->nz, mesh->xn, mesh->yn, mesh->zn};
+    const Obs o{obs->n, obs->x, obs->y, obs->z};
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st, {});
+    if (rc) return rc;
+
+    const MultiPlan mp = plan_multi(g, o.n);
+    Arena ar = ctx_arena(ctx);
+    const size_t packed = (size_t)mp.nblk * g.nz * kModels * kPrismsPerStep;
+    __bf16 *bhi = nullptr, *blo = nullptr;
+    float *b32 = nullptr;
+    if (prec == GRAV_MIXED_BF16X3) {
+        bhi = ar.take<__bf16>(packed);
+        blo = ar.take<__bf16>(packed);
+    } else {
+        b32 = ar.take<float>(packed);
+    }
+    float *hk = ar.take<float>(g.nz);
+    double *part = ar.take<double>((size_t)mp.nchunk * o.n * kModels);
+    if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the multi-model forward");
+
+    k_layer_thickness_m<<<(unsigned)cdiv(g.nz, 256), 256, 0, st>>>(g.zn, g.nz, hk);
+    if (prec == GRAV_MIXED_BF16X3)
+        k_pack_models_bf16<<<grid_cap((int64_t)packed), 256, 0, st>>>(models, K, g.nx, g.ny, g.nz,
+                                                                     mp.nby, (int64_t)packed, bhi, blo);
+    else
+        k_pack_models_f32<<<grid_cap((int64_t)packed), 256, 0, st>>>(models, K, g.nx, g.ny, g.nz,
+                                                                    mp.nby, (int64_t)packed, b32);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "pack models");
+    const unsigned blocks = (unsigned)(mp.ntile * mp.nchunk);
+    {
+        KernelTimer kt(ctx, prec == GRAV_MIXED_BF16X3 ? "multi_bf16x3" : "multi_fp32", st);
+        if (prec == GRAV_MIXED_BF16X3)
+            k_forward_multi<true><<<blocks, 256, 0, st>>>(g.xn, g.yn, g.zn, g.nx, g.ny, g.nz, hk, o.x,
+                                                          o.y, o.z, o.n, bhi, blo, nullptr, mp.nby,
+                                                          mp.nblk, mp.blocks_per_chunk, mp.nchunk,
+                                                          part);
+        else
+            k_forward_multi<false><<<blocks, 256, 0, st>>>(g.xn, g.yn, g.zn, g.nx, g.ny, g.nz, hk, o.x,
+                                                           o.y, o.z, o.n, nullptr, nullptr, b32, mp.nby,
+                                                           mp.nblk, mp.blocks_per_chunk, mp.nchunk,
+                                                           part);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, "multi-model sweep");
+    }
+    k_reduce_multi<<<grid_cap(o.n * K), 256, 0, st>>>(part, mp.nchunk, o.n, K, GRAV_GAMMA, D);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "multi-model reduce");
+    return GRAV_OK;
 }

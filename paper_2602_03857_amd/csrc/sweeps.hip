@@ -178,16 +178,13 @@ __global__ __launch_bounds__(kBlock) void k_forward_mixed(
     int a = (int)(c0 / ny1), b = (int)(c0 - (int64_t)a * ny1);
     for (int64_t col = c0; col < c1; ++col) {
         const Column c = make_column(xn[a], yn[b], xo, yo);
-        float z1 = ztop;
-        float R1 = node_radius(c, z1);
+        Node top = make_node(c, ztop);
         const double *__restrict__ w = w2 + col * nz;
         for (int k = 0; k < nz; ++k) {
-            const float z2 = static_cast<float>(zn[k + 1] - zo);
-            const float R2 = node_radius(c, z2);
-            const float S = edge_segment(c, z1, z2, hk[k], R1, R2);
+            const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
+            const float S = edge_segment(c, top, bot, hk[k]);
             acc = fma(static_cast<double>(S), w[k], acc);
-            z1 = z2;
-            R1 = R2;
+            top = bot;
         }
         if (++b == ny1) { b = 0; ++a; }
     }
@@ -251,17 +248,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_mixed(
     for (int64_t o = o0; o < o1; ++o) {
         const double xo = ox[o], yo = oy[o], zo = oz[o], vo = v[o];
         const Column c = make_column(X, Y, xo, yo);
-        float z1 = static_cast<float>(zn[k0] - zo);
-        float R1 = node_radius(c, z1);
+        Node top = make_node(c, static_cast<float>(zn[k0] - zo));
 #pragma unroll
         for (int j = 0; j < kAdjLayers; ++j) {
             if (j < cnt) {
-                const float z2 = static_cast<float>(zn[k0 + j + 1] - zo);
-                const float R2 = node_radius(c, z2);
-                const float S = edge_segment(c, z1, z2, h[j], R1, R2);
+                const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
+                const float S = edge_segment(c, top, bot, h[j]);
                 acc[j] = fma(vo, static_cast<double>(S), acc[j]);
-                z1 = z2;
-                R1 = R2;
+                top = bot;
             }
         }
     }
@@ -319,13 +313,13 @@ __global__ __launch_bounds__(kBlock) void k_trace_mixed(
             const float h = hk[k];
             Column ca = make_column(Xa, yn[0], xo, yo);
             Column cb = make_column(Xb, yn[0], xo, yo);
-            float Sa = edge_segment(ca, z1, z2, h, node_radius(ca, z1), node_radius(ca, z2));
-            float Sb = edge_segment(cb, z1, z2, h, node_radius(cb, z1), node_radius(cb, z2));
+            float Sa = edge_segment(ca, make_node(ca, z1), make_node(ca, z2), h);
+            float Sb = edge_segment(cb, make_node(cb, z1), make_node(cb, z2), h);
             for (int j = 0; j < ny; ++j) {
                 ca = make_column(Xa, yn[j + 1], xo, yo);
                 cb = make_column(Xb, yn[j + 1], xo, yo);
-                const float Sa1 = edge_segment(ca, z1, z2, h, node_radius(ca, z1), node_radius(ca, z2));
-                const float Sb1 = edge_segment(cb, z1, z2, h, node_radius(cb, z1), node_radius(cb, z2));
+                const float Sa1 = edge_segment(ca, make_node(ca, z1), make_node(ca, z2), h);
+                const float Sb1 = edge_segment(cb, make_node(cb, z1), make_node(cb, z2), h);
                 const double g = ((double)Sa - (double)Sb) - ((double)Sa1 - (double)Sb1);
                 const double w = wdepth[((int64_t)i * ny + j) * nz + k];
                 acc = fma(g * g, 1.0 / (w * w), acc);

@@ -81,6 +81,52 @@ def test_forward_config1(g, ctx, prec_name):
     assert np.max(np.abs(d - ref)) <= 10 * (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED) * np.max(np.abs(ref))
 
 
+def _single_prism_positions():
+    """Observation points around one prism: on its corners, edges and top
+    face, and on shells at R/a = 0.5 ... 30 (all on or above the top)."""
+    xs, ys, top = (0.0, 100.0), (0.0, 60.0), 20.0
+    pts = []
+    for x in (-50.0, 0.0, 37.0, 100.0, 160.0):
+        for y in (-30.0, 0.0, 22.0, 60.0, 95.0):
+            for h in (0.0, 1.0, 30.0):
+                pts.append((x, y, top - h))
+    rng = np.random.default_rng(42)
+    c = np.array([50.0, 30.0, 55.0])
+    for ratio in (0.5, 1.0, 3.0, 10.0, 30.0):
+        for _ in range(40):
+            d = rng.standard_normal(3)
+            d[2] = -abs(d[2])
+            d /= np.linalg.norm(d)
+            o = c + ratio * 100.0 * d
+            o[2] = min(o[2], top)
+            pts.append(tuple(o))
+    pts = np.array(pts)
+    mesh = workloads.Mesh(np.array(xs), np.array(ys), np.array([top, 90.0]))
+    return mesh, workloads.Survey(pts[:, 0], pts[:, 1], pts[:, 2])
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_single_prism_singular_and_far_positions(g, ctx, prec_name):
+    """Per point, one prism: the FP32 edge form loses accuracy like
+    eps32 * (R/a)^2 (the (x, y) parity sum of four edge terms), so the bound
+    is max(2e-6, 3e-7 (R/a)^2) relative; FP64 must match to 1e-9."""
+    mesh_h, obs_h = _single_prism_positions()
+    mesh, obs = g.DeviceMesh.from_mesh(mesh_h), g.DeviceObs.from_survey(obs_h)
+    m = np.array([1000.0])
+    d = to_np(ctx.forward(mesh, obs, _t(m), prec=getattr(g, prec_name)))
+    ref = prism.forward_literal(mesh_h, obs_h, m)
+    R = np.sqrt((obs_h.x - 50.0) ** 2 + (obs_h.y - 30.0) ** 2 + (obs_h.z - 55.0) ** 2)
+    ratio = np.maximum(R / 100.0, 1.0)
+    rel = np.abs(d - ref) / np.abs(ref)
+    bound = 1e-9 if prec_name == "GRAV_FP64" else np.maximum(2e-6, 3e-7 * ratio ** 2)
+    worst = int(np.argmax(rel / bound))
+    print(f"[parity] single prism {prec_name}: worst rel {rel[worst]:.2e} at "
+          f"{obs_h.x[worst], obs_h.y[worst], obs_h.z[worst]} bound {np.broadcast_to(bound, rel.shape)[worst]:.1e}",
+          flush=True)
+    assert np.all(np.isfinite(d))
+    assert np.all(rel <= bound)
+
+
 # ------------------------------------------------------------------ adjoint
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
@@ -240,6 +286,58 @@ def test_config4_forward_sampled_rows(g, ctx):
     err = rel_l2(gt[gold["cells"]], gold["gtv"])
     _report("config4 adjoint GRAV_MIXED (48 cells)", err)
     assert err <= TOL_MIXED
+
+
+# ------------------------------------------------------------------ multi-model
+
+TOL_MULTI = 1e-4   # per-model relative L2 of the split-bf16 / FP32 G-tile contraction
+
+
+def _blocky_models(mesh, K, seed):
+    rng = np.random.default_rng(seed)
+    wx = mesh.xn[-1] - mesh.xn[0]
+    cols = [workloads.ellipsoid_model(mesh, rng, 3, 0.1 * wx, 0.6 * wx) + 20.0 * rng.standard_normal(mesh.ncells)
+            for _ in range(K)]
+    return np.ascontiguousarray(np.stack(cols, axis=1).astype(np.float32))
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_MIXED_BF16X3", "GRAV_FP32_VALU"])
+@pytest.mark.parametrize("case", [
+    dict(seed=21, nx=9, ny=6, nz=5, n=130, K=5),
+    dict(seed=22, nx=17, ny=13, nz=11, n=70, K=64),
+    dict(seed=23, nx=4, ny=4, nz=2, n=64, K=1),
+])
+def test_forward_multi_per_model(g, ctx, prec_name, case):
+    import torch
+    p = workloads.random_case(case["seed"], case["nx"], case["ny"], case["nz"], case["n"], on_top=10,
+                              on_nodes=5)
+    models = _blocky_models(p.mesh, case["K"], case["seed"])
+    mesh, obs = _dev(g, p)
+    D = to_np(ctx.forward_multi(mesh, obs, torch.as_tensor(models, device="cuda"),
+                                prec=getattr(g, prec_name)))
+    ref = prism.forward_multi(p.mesh, p.obs, models.astype(np.float64))
+    errs = np.linalg.norm(D - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    print(f"[parity] multi {prec_name} {case}: per-model rel L2 max {errs.max():.2e} "
+          f"median {np.median(errs):.2e}", flush=True)
+    assert np.all(errs <= TOL_MULTI)
+
+
+def test_forward_multi_config3_sampled_rows(g, ctx):
+    """64 models on the 500k-cell mesh with 10,000 observations; 48 seeded rows
+    per model against the FP64 oracle, for both contraction paths."""
+    import torch
+    p = workloads.config2()
+    models = workloads.config3_models(p.mesh).astype(np.float32)
+    rows = np.sort(np.random.default_rng(333).choice(p.obs.n, 48, replace=False))
+    ref = prism.forward_multi(p.mesh, p.obs, models.astype(np.float64), rows=rows)
+    mesh, obs = _dev(g, p)
+    mt = torch.as_tensor(models, device="cuda")
+    for prec_name in ("GRAV_MIXED_BF16X3", "GRAV_FP32_VALU"):
+        D = to_np(ctx.forward_multi(mesh, obs, mt, prec=getattr(g, prec_name)))[rows]
+        errs = np.linalg.norm(D - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        print(f"[parity] config3 multi {prec_name}: per-model rel L2 max {errs.max():.2e} "
+              f"median {np.median(errs):.2e}", flush=True)
+        assert np.all(errs <= TOL_MULTI)
 
 
 # ------------------------------------------------------------------ determinism and errors
