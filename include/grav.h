@@ -196,6 +196,80 @@ int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs
 
 
 /* ---------------------------------------------------------------------------
+ * Serving: continuous batching of forward and inversion requests on one GPU
+ * (GRAV_MIXED precision).  A worker thread owns a device memory pool of
+ * `budget_bytes`; queued requests are admitted in arrival order while their
+ * state (O(N + M) per request: partial sums, CG vectors) fits in the pool and
+ * fewer than `max_active` are in flight.  Every scheduling step issues one
+ * batched launch per sweep type that covers the blocks of all active
+ * requests, so each active inversion advances one CG iteration per step and
+ * requests that arrive meanwhile join at the next step.  A request's launch
+ * plan depends only on its own shape, so its result is bitwise the same alone
+ * and in any mix, and the same as grav_forward / grav_invert (GRAV_MIXED).
+ * Requests may be submitted from any thread.
+ * ------------------------------------------------------------------------ */
+typedef struct grav_server grav_server;
+
+typedef enum { GRAV_REQ_FORWARD = 0, GRAV_REQ_INVERT = 1 } grav_req_kind;
+
+typedef struct {
+    int32_t device;         /* HIP device ordinal */
+    int32_t max_active;     /* requests in flight at once; 0 = 64 (max 256) */
+    uint64_t budget_bytes;  /* device memory for request state; 0 = 16 GiB */
+} grav_server_opts;
+
+/* One request.  All arrays are caller-owned DEVICE pointers that must stay
+ * valid and unmodified until the request is reported done.
+ *   FORWARD: m (M) -> d (n), d = G m.
+ *   INVERT : d_obs (n), wdepth (M, > 0), lambda (< 0 = 1e-2 trace/n), cg
+ *            options -> m_out (M) = C G^T y, y the CG solution of
+ *            (G C G^T + lambda I) y = d_obs (reference model 0). */
+typedef struct {
+    int32_t kind;            /* grav_req_kind */
+    grav_mesh mesh;
+    grav_obs obs;
+    const double *m;
+    double *d;
+    const double *d_obs;
+    const double *wdepth;
+    double lambda;
+    grav_cg_opts cg;
+    double *m_out;
+} grav_request;
+
+typedef struct {
+    int32_t status;          /* GRAV_OK, GRAV_ENOCONV (max_iter reached) or an error */
+    int32_t iters;           /* CG iterations (inversions) */
+    double relres;           /* final relative residual (inversions) */
+    double lambda_used;      /* (inversions) */
+    double queue_ms;         /* submit -> admitted */
+    double run_ms;           /* admitted -> done (device work finished) */
+    uint64_t state_bytes;    /* pool bytes the request held */
+} grav_request_info;
+
+/* Create a server (allocates its pool, starts its worker thread).
+ * Errors: GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE. */
+int grav_server_create(grav_server **srv, const grav_server_opts *opts);
+
+/* Queue a request; *ticket identifies it.  The request is checked on the
+ * device before it is queued (same rules as grav_forward / grav_invert).
+ * Errors: GRAV_EINVAL (bad request), GRAV_ENOMEM (its state alone exceeds the
+ * pool), GRAV_EDEVICE. */
+int grav_server_submit(grav_server *srv, const grav_request *req, uint64_t *ticket);
+
+/* *done = 1 when the request has finished (outputs written and visible);
+ * then `info` (nullable) is filled and the ticket is retired.  Returns
+ * GRAV_OK, or GRAV_EINVAL for an unknown/retired ticket. */
+int grav_server_poll(grav_server *srv, uint64_t ticket, int32_t *done, grav_request_info *info);
+
+/* Block until the request has finished; fills `info` (nullable), retires the
+ * ticket, returns its status. */
+int grav_server_wait(grav_server *srv, uint64_t ticket, grav_request_info *info);
+
+/* Finish all admitted and queued requests, stop the worker, free the pool. */
+void grav_server_destroy(grav_server *srv);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics: per-kernel timing.  With timing enabled, the library records a
  * pair of HIP events on the call's stream around every launch of its sweep
  * kernels ("forward_mixed", "forward_f64", "adjoint_mixed", "adjoint_f64",

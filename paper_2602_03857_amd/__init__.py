@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     CMesh, CObs, CtxOpts, CgOpts, CgInfo,
 )
 from .api import Context, DeviceMesh, DeviceObs, workspace_bytes  # noqa: F401
+from .serve import Server  # noqa: F401
 
-__all__ = ["Context", "DeviceMesh", "DeviceObs", "workspace_bytes", "GravError", "lib",
+__all__ = ["Context", "Server", "DeviceMesh", "DeviceObs", "workspace_bytes", "GravError", "lib",
            "GRAV_FP64", "GRAV_MIXED", "GRAV_MIXED_BF16X3", "GRAV_FP32_VALU", "GRAV_GAMMA"]

@@ -39,6 +39,23 @@ class CgInfo(ctypes.Structure):
                 ("lambda_used", ctypes.c_double), ("trace", ctypes.c_double)]
 
 
+class GravRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("mesh", CMesh), ("obs", CObs), ("m", ctypes.c_void_p),
+                ("d", ctypes.c_void_p), ("d_obs", ctypes.c_void_p), ("wdepth", ctypes.c_void_p),
+                ("lam", ctypes.c_double), ("cg", CgOpts), ("m_out", ctypes.c_void_p)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("lambda_used", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("state_bytes", ctypes.c_uint64)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_uint64)]
+
+
 class GravError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"grav error {code}: {msg}")
@@ -73,6 +90,11 @@ def _load():
                                        P(CgInfo), ctypes.c_int, vp]),
         "grav_forward_multi": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, i32, vp, ctypes.c_int,
                                               vp]),
+        "grav_server_create": (ctypes.c_int, [P(vp), P(ServerOpts)]),
+        "grav_server_submit": (ctypes.c_int, [vp, P(GravRequest), P(ctypes.c_uint64)]),
+        "grav_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, P(i32), P(RequestInfo)]),
+        "grav_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, P(RequestInfo)]),
+        "grav_server_destroy": (None, [vp]),
         "grav_set_timing": (ctypes.c_int, [vp, i32]),
         "grav_kernel_time": (ctypes.c_int, [vp, ctypes.c_char_p, P(dbl), P(i64)]),
         "grav_reset_timing": (ctypes.c_int, [vp]),
@@ -90,5 +112,6 @@ EXPORTED = [
     "grav_ctx_opts_default", "grav_ctx_create", "grav_ctx_destroy", "grav_last_error",
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
     "grav_invert", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
-    "grav_reset_timing",
+    "grav_reset_timing", "grav_server_create", "grav_server_submit", "grav_server_poll",
+    "grav_server_wait", "grav_server_destroy",
 ]

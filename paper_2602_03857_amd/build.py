@@ -23,7 +23,7 @@ SOURCES = ["api.hip", "sweeps.hip", "vec.hip", "solver.hip", "multi.hip", "serve
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=on", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-Wno-unused-command-line-argument",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 

@@ -1,0 +1,90 @@
+// Per-block bodies of the mixed-precision sweeps, shared by the single-call
+// kernels and by the server's batched multi-request kernels so that both run
+// exactly the same arithmetic for a given request and launch plan.
+#pragma once
+
+#include "grav_internal.h"
+#include "edge_math.h"
+
+namespace grav {
+
+// Forward sweep, one block: observations oblk*kBlock + [0, kBlock) against node
+// columns [chunk*cols_per_chunk, ...), writing partial[chunk*n + o] =
+// sum over the chunk's segments of S * W2 (FP64 accumulation).
+__device__ __forceinline__ void forward_mixed_block(
+    const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
+    int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
+    const double *__restrict__ oy, const double *__restrict__ oz, int64_t n,
+    const double *__restrict__ w2, int64_t ncols, int64_t cols_per_chunk, int chunk, int64_t oblk,
+    double *__restrict__ partial) {
+    const int64_t o = oblk * kBlock + threadIdx.x;
+    const int64_t oc = o < n ? o : n - 1;
+    const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
+    const float ztop = static_cast<float>(zn[0] - zo);
+    const int64_t c0 = (int64_t)chunk * cols_per_chunk;
+    const int64_t c1 = c0 + cols_per_chunk < ncols ? c0 + cols_per_chunk : ncols;
+    double acc = 0.0;
+    int a = (int)(c0 / ny1), b = (int)(c0 - (int64_t)a * ny1);
+    for (int64_t col = c0; col < c1; ++col) {
+        const Column c = make_column(xn[a], yn[b], xo, yo);
+        Node top = make_node(c, ztop);
+        const double *__restrict__ w = w2 + col * nz;
+        for (int k = 0; k < nz; ++k) {
+            const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
+            const float S = edge_segment(c, top, bot, hk[k]);
+            acc = fma(static_cast<double>(S), w[k], acc);
+            top = bot;
+        }
+        if (++b == ny1) { b = 0; ++a; }
+    }
+    if (o < n) partial[(int64_t)chunk * n + o] = acc;
+}
+
+// Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane, layer
+// chunk kc (of nkc, <= kAdjLayers layers), observations of part `part`;
+// writes upart[part][segment] = sum_{o in part} v_o S (FP64, one register
+// pair per layer, no cross-lane reduction).
+__device__ __forceinline__ void adjoint_mixed_block(
+    const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
+    int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
+    const double *__restrict__ oy, const double *__restrict__ oz, const double *__restrict__ v,
+    int64_t n, int64_t obs_per_part, int64_t ncols, int nkc, int part, int kc, int64_t colblk,
+    double *__restrict__ upart) {
+    const int64_t col = colblk * kBlock + threadIdx.x;
+    const int64_t colc = col < ncols ? col : ncols - 1;
+    const int a = (int)(colc / ny1);
+    const int b = (int)(colc - (int64_t)a * ny1);
+    const double X = xn[a], Y = yn[b];
+    const int k0 = (int)((int64_t)kc * nz / nkc);
+    const int cnt = (int)((int64_t)(kc + 1) * nz / nkc) - k0;
+    float h[kAdjLayers];
+#pragma unroll
+    for (int j = 0; j < kAdjLayers; ++j) h[j] = j < cnt ? hk[k0 + j] : 1.0f;
+    double acc[kAdjLayers];
+#pragma unroll
+    for (int j = 0; j < kAdjLayers; ++j) acc[j] = 0.0;
+    const int64_t o0 = (int64_t)part * obs_per_part;
+    const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
+    for (int64_t o = o0; o < o1; ++o) {
+        const double xo = ox[o], yo = oy[o], zo = oz[o], vo = v[o];
+        const Column c = make_column(X, Y, xo, yo);
+        Node top = make_node(c, static_cast<float>(zn[k0] - zo));
+#pragma unroll
+        for (int j = 0; j < kAdjLayers; ++j) {
+            if (j < cnt) {
+                const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
+                const float S = edge_segment(c, top, bot, h[j]);
+                acc[j] = fma(vo, static_cast<double>(S), acc[j]);
+                top = bot;
+            }
+        }
+    }
+    if (col < ncols) {
+        double *__restrict__ dst = upart + (int64_t)part * ncols * nz + col * nz + k0;
+#pragma unroll
+        for (int j = 0; j < kAdjLayers; ++j)
+            if (j < cnt) dst[j] = acc[j];
+    }
+}
+
+}  // namespace grav

@@ -23,6 +23,7 @@
 // d_o = gamma * sum_nodes Psi(node - o) * W.
 #include "grav_internal.h"
 #include "edge_math.h"
+#include "sweep_bodies.h"
 
 namespace grav {
 
@@ -167,28 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_mixed(
     const double *__restrict__ oy, const double *__restrict__ oz, int64_t n,
     const double *__restrict__ w2, int64_t ncols, int64_t cols_per_chunk, int nchunk,
     double *__restrict__ partial) {
-    const int chunk = (int)(blockIdx.x % nchunk);
-    const int64_t o = (int64_t)(blockIdx.x / nchunk) * kBlock + threadIdx.x;
-    const int64_t oc = o < n ? o : n - 1;
-    const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
-    const float ztop = static_cast<float>(zn[0] - zo);
-    const int64_t c0 = (int64_t)chunk * cols_per_chunk;
-    const int64_t c1 = c0 + cols_per_chunk < ncols ? c0 + cols_per_chunk : ncols;
-    double acc = 0.0;
-    int a = (int)(c0 / ny1), b = (int)(c0 - (int64_t)a * ny1);
-    for (int64_t col = c0; col < c1; ++col) {
-        const Column c = make_column(xn[a], yn[b], xo, yo);
-        Node top = make_node(c, ztop);
-        const double *__restrict__ w = w2 + col * nz;
-        for (int k = 0; k < nz; ++k) {
-            const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
-            const float S = edge_segment(c, top, bot, hk[k]);
-            acc = fma(static_cast<double>(S), w[k], acc);
-            top = bot;
-        }
-        if (++b == ny1) { b = 0; ++a; }
-    }
-    if (o < n) partial[(int64_t)chunk * n + o] = acc;
+    forward_mixed_block(xn, yn, zn, ny1, nz, hk, ox, oy, oz, n, w2, ncols, cols_per_chunk,
+                        (int)(blockIdx.x % nchunk), (int64_t)(blockIdx.x / nchunk), partial);
 }
 
 // FP64 forward sweep over nodes: lane = observation, chunk of node columns.
@@ -215,10 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_f64(
     if (o < n) partial[(int64_t)chunk * n + o] = acc;
 }
 
-// Mixed adjoint sweep.  Lane = (node column, chunk of <= kAdjLayers layers);
-// every lane of a block shares the layer chunk and the observation part, so
-// the observation data and depths are wave-uniform.  U accumulates in FP64,
-// one register pair per layer; no reductions across lanes are needed.
+// Mixed adjoint sweep.  Lane = (node column, chunk of <= kAdjLayers layers).
 __global__ __launch_bounds__(kBlock) void k_adjoint_mixed(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
@@ -230,41 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_mixed(
     bid /= nparts;
     const int kc = (int)(bid % nkc);
     bid /= nkc;
-    const int64_t col = bid * kBlock + threadIdx.x;
-    const int64_t colc = col < ncols ? col : ncols - 1;
-    const int a = (int)(colc / ny1);
-    const int b = (int)(colc - (int64_t)a * ny1);
-    const double X = xn[a], Y = yn[b];
-    const int k0 = (int)((int64_t)kc * nz / nkc);
-    const int cnt = (int)((int64_t)(kc + 1) * nz / nkc) - k0;
-    float h[kAdjLayers];
-#pragma unroll
-    for (int j = 0; j < kAdjLayers; ++j) h[j] = j < cnt ? hk[k0 + j] : 1.0f;
-    double acc[kAdjLayers];
-#pragma unroll
-    for (int j = 0; j < kAdjLayers; ++j) acc[j] = 0.0;
-    const int64_t o0 = (int64_t)part * obs_per_part;
-    const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
-    for (int64_t o = o0; o < o1; ++o) {
-        const double xo = ox[o], yo = oy[o], zo = oz[o], vo = v[o];
-        const Column c = make_column(X, Y, xo, yo);
-        Node top = make_node(c, static_cast<float>(zn[k0] - zo));
-#pragma unroll
-        for (int j = 0; j < kAdjLayers; ++j) {
-            if (j < cnt) {
-                const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
-                const float S = edge_segment(c, top, bot, h[j]);
-                acc[j] = fma(vo, static_cast<double>(S), acc[j]);
-                top = bot;
-            }
-        }
-    }
-    if (col < ncols) {
-        double *__restrict__ dst = upart + (int64_t)part * ncols * nz + col * nz + k0;
-#pragma unroll
-        for (int j = 0; j < kAdjLayers; ++j)
-            if (j < cnt) dst[j] = acc[j];
-    }
+    adjoint_mixed_block(xn, yn, zn, ny1, nz, hk, ox, oy, oz, v, n, obs_per_part, ncols, nkc, part,
+                        kc, bid, upart);
 }
 
 // FP64 adjoint sweep: lane = node, P(node) = sum_{o in part} v_o Psi(node - o).

@@ -47,13 +47,13 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double *__restrict__ p
                 scal[kB2] = s;
                 scal[kRRNew] = s;
                 break;
-            case kFinishPQ:            // alpha = (r.r) / (p.Ap)
+            case kFinishPQ:            // alpha = (r.r) / (p.Ap); 0 once r = 0
                 scal[kPQ] = s;
-                scal[kAlpha] = scal[kRR] / s;
+                scal[kAlpha] = s > 0.0 ? scal[kRR] / s : 0.0;
                 break;
             case kFinishRRNew:         // beta = (r'.r') / (r.r), then r.r <- r'.r'
                 scal[kRRNew] = s;
-                scal[kBeta] = s / scal[kRR];
+                scal[kBeta] = scal[kRR] > 0.0 ? s / scal[kRR] : 0.0;
                 scal[kRR] = s;
                 break;
             default:

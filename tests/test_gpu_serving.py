@@ -1,0 +1,136 @@
+"""GPU tests of the continuous-batching server: a request's result is the
+same (bitwise) alone and in a mix, equals the single-call operators, memory
+admission queues instead of failing, and bad requests are rejected."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import prism, inversion
+from tests._util import load_package, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    pkg = load_package()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return pkg
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _requests():
+    """A mix of uneven shapes: forward and inversion problems."""
+    cases = []
+    for seed, (nx, ny, nz, n, kind) in enumerate([(14, 12, 6, 300, "inv"), (20, 9, 11, 77, "fwd"),
+                                                   (8, 8, 8, 130, "inv"), (31, 17, 5, 500, "fwd"),
+                                                   (10, 12, 7, 64, "inv")]):
+        p = workloads.random_case(100 + seed, nx, ny, nz, n, model="blocky", on_top=n // 5)
+        cases.append((kind, p))
+    return cases
+
+
+def _device_problem(g, kind, p):
+    import torch
+    mesh, obs = g.DeviceMesh.from_mesh(p.mesh), g.DeviceObs.from_survey(p.obs)
+    if kind == "fwd":
+        return dict(mesh=mesh, obs=obs, m=_t(p.m), d=torch.empty(p.obs.n, dtype=torch.float64, device="cuda"))
+    d_clean = prism.forward(p.mesh, p.obs, p.m)
+    d_obs = inversion.add_noise(d_clean, p.noise_draws, 0.01)
+    return dict(mesh=mesh, obs=obs, d_obs=_t(d_obs), w=_t(p.wdepth),
+                m_out=torch.empty(p.mesh.ncells, dtype=torch.float64, device="cuda"))
+
+
+def _submit(srv, kind, dp, tol=1e-8, max_iter=300):
+    if kind == "fwd":
+        return srv.submit_forward(dp["mesh"], dp["obs"], dp["m"], dp["d"])
+    return srv.submit_invert(dp["mesh"], dp["obs"], dp["d_obs"], dp["w"], dp["m_out"], lam=-1.0,
+                             tol=tol, max_iter=max_iter)
+
+
+def _result(kind, dp):
+    return to_np(dp["d"] if kind == "fwd" else dp["m_out"]).copy()
+
+
+def test_results_identical_alone_and_in_mix(g):
+    cases = _requests()
+    alone = []
+    with g.Server(0, budget_bytes=1 << 30) as srv:
+        for kind, p in cases:
+            dp = _device_problem(g, kind, p)
+            info = srv.wait(_submit(srv, kind, dp))
+            alone.append((_result(kind, dp), info))
+        mixed = [_device_problem(g, kind, p) for kind, p in cases]
+        tickets = [_submit(srv, kind, dp) for (kind, _), dp in zip(cases, mixed)]
+        infos = [srv.wait(t) for t in tickets]
+    for (kind, _), dp, (ref, info_a), info_m in zip(cases, mixed, alone, infos):
+        assert np.array_equal(_result(kind, dp), ref), kind
+        assert info_a["iters"] == info_m["iters"]
+        print(f"[serving] {kind}: iters {info_m['iters']} relres {info_m['relres']:.2e} "
+              f"queue {info_m['queue_ms']:.1f} ms run {info_m['run_ms']:.1f} ms", flush=True)
+
+
+def test_served_equals_single_call_operators(g):
+    import torch
+    cases = _requests()
+    ctx = g.Context(0)
+    with g.Server(0, budget_bytes=1 << 30) as srv:
+        dps = [_device_problem(g, kind, p) for kind, p in cases]
+        tickets = [_submit(srv, kind, dp) for (kind, _), dp in zip(cases, dps)]
+        infos = [srv.wait(t) for t in tickets]
+    for (kind, p), dp, info in zip(cases, dps, infos):
+        if kind == "fwd":
+            d = ctx.forward(dp["mesh"], dp["obs"], dp["m"], prec=g.GRAV_MIXED)
+            assert torch.equal(d, dp["d"])
+            assert rel_l2(to_np(d), prism.forward(p.mesh, p.obs, p.m)) <= 1e-5
+        else:
+            m, _, inf = ctx.invert(dp["mesh"], dp["obs"], dp["d_obs"], dp["w"], lam=-1.0, tol=1e-8,
+                                   max_iter=300, prec=g.GRAV_MIXED)
+            assert inf["iters"] == info["iters"]
+            assert abs(inf["lambda_used"] - info["lambda_used"]) <= 1e-12 * inf["lambda_used"]
+            assert torch.equal(m, dp["m_out"])
+    ctx.close()
+
+
+def test_admission_by_memory_queues_instead_of_failing(g):
+    cases = _requests()
+    with g.Server(0, budget_bytes=1 << 30) as probe:
+        sizes = []
+        for kind, p in cases:
+            dp = _device_problem(g, kind, p)
+            sizes.append(probe.wait(_submit(probe, kind, dp))["state_bytes"])
+    budget = max(sizes) + 4096          # room for the largest request, rarely for two
+    with g.Server(0, budget_bytes=budget) as srv:
+        dps = [_device_problem(g, kind, p) for kind, p in cases]
+        tickets = [_submit(srv, kind, dp) for (kind, _), dp in zip(cases, dps)]
+        infos = [srv.wait(t) for t in tickets]
+    assert all(i["status"] in (0, 4) for i in infos)
+    assert max(i["queue_ms"] for i in infos) > 0.0
+
+
+def test_bad_requests_rejected(g):
+    import torch
+    p = workloads.random_case(7, 5, 5, 4, 20)
+    with g.Server(0, budget_bytes=64 << 20) as srv:
+        bad_obs = g.DeviceObs(p.obs.x, p.obs.y, p.obs.z + 1e4)
+        mesh = g.DeviceMesh.from_mesh(p.mesh)
+        d = torch.empty(p.obs.n, dtype=torch.float64, device="cuda")
+        with pytest.raises(g.GravError) as e:
+            srv.submit_forward(mesh, bad_obs, _t(p.m), d)
+        assert e.value.code == g.GRAV_EINVAL
+        big = workloads.random_case(8, 120, 120, 60, 4000)
+        bm, bo = g.DeviceMesh.from_mesh(big.mesh), g.DeviceObs.from_survey(big.obs)
+        with pytest.raises(g.GravError) as e:
+            srv.submit_invert(bm, bo, _t(np.ones(big.obs.n)), _t(big.wdepth),
+                              torch.empty(big.mesh.ncells, dtype=torch.float64, device="cuda"))
+        assert e.value.code == g.GRAV_ENOMEM
+        # the server still works after rejections
+        obs = g.DeviceObs.from_survey(p.obs)
+        t = srv.submit_forward(mesh, obs, _t(p.m), d)
+        srv.wait(t)
+        assert rel_l2(to_np(d), prism.forward(p.mesh, p.obs, p.m)) <= 1e-5
