@@ -31,13 +31,35 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 
-# Peak VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-slot
-# per cycle for a full-rate (non-packed FP32 / FP64) instruction.
-PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU lane-slots per vertical edge segment of the forward sweep:
-# the minimal gfx950 instruction sequence of the edge-segment formula
-# (derivation and per-operation table in the design notes).
-SLOTS_PER_SEGMENT = 96
+# Roofline of the forward sweep (an instruction-issue-bound kernel).
+# Peak: MI355X FP32 vector 157.3 TFLOP/s = 78.65e12 full-rate lane operations
+# per second (FMA = one operation).  Algorithmic cost of one (observation,
+# vertical edge segment) pair: the minimal gfx950 instruction sequence of the
+# edge-segment formula (per-operation table in the design notes), 94
+# instructions for layers near the top and 84 for "deep" layers (top at least
+# 9 thicknesses below the mesh top, where the atan difference needs no range
+# reduction).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log; measured to
+# issue at 1/4 of the FMA rate) and 2 are FP64 (half rate); issue slots per
+# pair = instructions + 3 * 6 + 1 * 2.
+PEAK_SLOTS = 157.3e12 / 2.0
+INSTR_SHALLOW, INSTR_DEEP = 94, 84
+N_TRANS, N_FP64 = 6, 2
+TRANS_COST, FP64_COST = 4, 2
+DEEP_RATIO = 9.0
+
+
+def slots_per_pair(instr: int) -> int:
+    return instr + N_TRANS * (TRANS_COST - 1) + N_FP64 * (FP64_COST - 1)
+
+
+def first_deep_layer(zn) -> int:
+    """Same rule as the library: every layer from this index on has its top at
+    least DEEP_RATIO thicknesses below the mesh top."""
+    k = len(zn) - 1
+    while k > 0 and (zn[k - 1] - zn[0]) >= DEEP_RATIO * (zn[k] - zn[k - 1]):
+        k -= 1
+    return k
+
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_mixed_config4_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_03857_amd", "csrc", f)
@@ -53,22 +75,176 @@ def kernel_source_hash() -> str:
 
 
 def cpu_baseline(p, target_s: float, workers: int):
-    """FP64 oracle (as it stands) on a bounded sample of config-4 rows."""
+    """FP64 oracle (as it stands) on a bounded sample of config-4 rows: batches
+    of seeded rows until about target_s seconds of wall time."""
     from oracle import parallel
     rng = np.random.default_rng(777)
-    rows_probe = rng.choice(p.obs.n, workers, replace=False)
-    t0 = time.perf_counter()
-    parallel.forward_rows(p.mesh, p.obs, p.m, rows_probe, workers=workers)
-    t_probe = time.perf_counter() - t0
-    n_rows = int(max(workers, min(4096, workers * max(1, round(target_s / max(t_probe, 1e-3))))))
-    rows = rng.choice(p.obs.n, n_rows, replace=False)
-    t0 = time.perf_counter()
-    parallel.forward_rows(p.mesh, p.obs, p.m, rows, workers=workers)
-    dt = time.perf_counter() - t0
-    pairs = n_rows * p.mesh.ncells
+    order = rng.permutation(p.obs.n)
+    batch = 8 * workers
+    done, dt = 0, 0.0
+    while dt < target_s and done + batch <= p.obs.n:
+        rows = order[done:done + batch]
+        t0 = time.perf_counter()
+        parallel.forward_rows(p.mesh, p.obs, p.m, rows, workers=workers)
+        dt += time.perf_counter() - t0
+        done += batch
+    pairs = done * p.mesh.ncells
     return {"value": pairs / dt, "unit": "pairs/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n_rows} rows of G m (each over all {p.mesh.ncells} prisms), "
+            "sample": f"{done} seeded rows of G m (each over all {p.mesh.ncells} prisms), "
                       f"FP64 NumPy node-shared oracle, {workers} processes, {dt:.1f} s"}
+
+
+def multi_model_extras(g, torch, dev):
+    """64 density models on the 500k-cell mesh with 10,000 observations:
+    split-bf16 MFMA and FP32-VALU contractions against 64 single forwards."""
+    p3 = workloads.config2()
+    models = workloads.config3_models(p3.mesh).astype(np.float32)
+    mesh = g.DeviceMesh.from_mesh(p3.mesh, dev)
+    obs = g.DeviceObs.from_survey(p3.obs, dev)
+    mt = torch.as_tensor(models, device=dev)
+    D = torch.empty((p3.obs.n, models.shape[1]), dtype=torch.float32, device=dev)
+    ctx = g.Context(0, validate=False)
+    ctx.set_timing(True)
+    res = {}
+    for prec, key in ((g.GRAV_MIXED_BF16X3, "multi_bf16x3"), (g.GRAV_FP32_VALU, "multi_fp32")):
+        ctx.forward_multi(mesh, obs, mt, D, prec=prec)
+        torch.cuda.synchronize()
+        ctx.reset_timing()
+        for _ in range(2):
+            ctx.forward_multi(mesh, obs, mt, D, prec=prec)
+        torch.cuda.synchronize()
+        ms, nl = ctx.kernel_time(key)
+        res[key + "_kernel_ms"] = ms / nl
+    m1 = torch.as_tensor(models[:, 0].astype(np.float64), device=dev)
+    d1 = torch.empty(p3.obs.n, dtype=torch.float64, device=dev)
+    ctx.forward(mesh, obs, m1, d1, prec=g.GRAV_MIXED)
+    torch.cuda.synchronize()
+    ctx.reset_timing()
+    for _ in range(3):
+        ctx.forward(mesh, obs, m1, d1, prec=g.GRAV_MIXED)
+    torch.cuda.synchronize()
+    ms, nl = ctx.kernel_time("forward_mixed")
+    single = ms / nl
+    pairs = p3.obs.n * p3.mesh.ncells * models.shape[1]
+    res["single_forward_kernel_ms"] = single
+    res["multi_speedup_vs_64_single_forwards"] = 64 * single / res["multi_bf16x3_kernel_ms"]
+    res["multi_bf16x3_model_pairs_per_s"] = pairs / (res["multi_bf16x3_kernel_ms"] * 1e-3)
+    ctx.close()
+    return res
+
+
+def _serve_inputs(g, torch, dev, reqs, ctx):
+    """Materialise the request stream on the device (not timed): meshes,
+    surveys, models; noisy data for inversions (d_clean from the library)."""
+    out = []
+    for r in reqs:
+        p = r["build"]()
+        mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
+        obs = g.DeviceObs.from_survey(p.obs, dev)
+        item = dict(t=r["t"], kind=r["kind"], mesh=mesh, obs=obs, n=p.obs.n, M=p.mesh.ncells)
+        m = torch.as_tensor(p.m, device=dev)
+        if r["kind"] == "forward":
+            item.update(m=m, d=torch.empty(p.obs.n, dtype=torch.float64, device=dev))
+        else:
+            d_clean = ctx.forward(mesh, obs, m, prec=g.GRAV_MIXED)
+            rms = torch.sqrt(torch.mean(d_clean * d_clean))
+            d_obs = d_clean + p.noise_level * rms * torch.as_tensor(p.noise_draws, device=dev)
+            item.update(d_obs=d_obs.contiguous(), w=torch.as_tensor(p.wdepth, device=dev),
+                        m_out=torch.empty(p.mesh.ncells, dtype=torch.float64, device=dev),
+                        tol=p.cg_tol, max_iter=p.cg_iters)
+        out.append(item)
+    torch.cuda.synchronize()
+    return out
+
+
+def _percentiles(lat):
+    lat = np.sort(np.asarray(lat))
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def run_serve(args) -> int:
+    """Replay the serving stream (Poisson arrivals) open-loop on wall-clock time
+    through the continuous-batching server, then the same arrivals through a
+    one-at-a-time FIFO of the plain FP64 single-call path."""
+    import torch
+    import paper_2602_03857_amd as g
+    dev = torch.device("cuda", 0)
+    reqs = workloads.config5_stream()[: args.serve_requests]
+    ctx = g.Context(0, validate=False)
+    items = _serve_inputs(g, torch, dev, reqs, ctx)
+    pairs = [it["n"] * it["M"] for it in items]
+    print(f"[serve] {len(items)} requests staged on the device", file=sys.stderr, flush=True)
+
+    # continuous batching
+    lat, iters = [None] * len(items), []
+    srv = g.Server(0, max_active=args.serve_max_active, budget_bytes=args.serve_budget_gb << 30)
+    t0 = time.perf_counter()
+    pending, nxt = {}, 0
+    while nxt < len(items) or pending:
+        now = time.perf_counter() - t0
+        while nxt < len(items) and items[nxt]["t"] <= now:
+            it = items[nxt]
+            if it["kind"] == "forward":
+                tk = srv.submit_forward(it["mesh"], it["obs"], it["m"], it["d"])
+            else:
+                tk = srv.submit_invert(it["mesh"], it["obs"], it["d_obs"], it["w"], it["m_out"],
+                                       lam=-1.0, tol=it["tol"], max_iter=it["max_iter"])
+            pending[tk] = nxt
+            nxt += 1
+        for tk in list(pending):
+            done, info = srv.poll(tk)
+            if done:
+                k = pending.pop(tk)
+                it = items[k]
+                _ = (it["d"] if it["kind"] == "forward" else it["m_out"]).cpu()
+                lat[k] = time.perf_counter() - t0 - it["t"]
+                if it["kind"] != "forward":
+                    iters.append(info["iters"])
+                ndone = sum(x is not None for x in lat)
+                if ndone % 20 == 0:
+                    print(f"[serve] {ndone} done", file=sys.stderr, flush=True)
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    srv.close()
+    p50, p99 = _percentiles(lat)
+    inv = [lat[i] for i, it in enumerate(items) if it["kind"] != "forward"]
+    i50, i99 = _percentiles(inv) if inv else (0.0, 0.0)
+    res = {"requests": len(items), "p50_s": p50, "p99_s": p99, "inversion_p50_s": i50,
+           "inversion_p99_s": i99, "wall_s": wall, "requests_per_s": len(items) / wall,
+           "pairs_per_s_forward_requests": sum(pairs[i] for i, it in enumerate(items)
+                                               if it["kind"] == "forward") / wall,
+           "mean_cg_iters": float(np.mean(iters)) if iters else 0}
+
+    # one-at-a-time FIFO of the plain FP64 path on the same arrivals
+    nb = min(args.serve_baseline_requests, len(items))
+    if nb > 0:
+        ctx64 = g.Context(0, validate=False)
+        lat_b = []
+        t0 = time.perf_counter()
+        for it in items[:nb]:
+            now = time.perf_counter() - t0
+            if now < it["t"]:
+                time.sleep(it["t"] - now)
+            if it["kind"] == "forward":
+                ctx64.forward(it["mesh"], it["obs"], it["m"], it["d"], prec=g.GRAV_FP64)
+                _ = it["d"].cpu()
+            else:
+                ctx64.invert(it["mesh"], it["obs"], it["d_obs"], it["w"], lam=-1.0, tol=it["tol"],
+                             max_iter=it["max_iter"], m_out=it["m_out"], prec=g.GRAV_FP64)
+                _ = it["m_out"].cpu()
+            lat_b.append(time.perf_counter() - t0 - it["t"])
+            print(f"[serve] fp64 fifo {len(lat_b)}/{nb}", file=sys.stderr, flush=True)
+        b50, b99 = _percentiles(lat_b)
+        s50, s99 = _percentiles(lat[:nb])
+        res["fp64_fifo_baseline"] = {"requests": nb, "p50_s": b50, "p99_s": b99,
+                                     "wall_s": time.perf_counter() - t0,
+                                     "batched_same_requests_p50_s": s50,
+                                     "batched_same_requests_p99_s": s99}
+        ctx64.close()
+    print(json.dumps({"metric": "CG solve p50/p99 latency, serving stream", "serving": res}),
+          flush=True)
+    ctx.close()
+    return 0
 
 
 def main() -> int:
@@ -80,7 +256,15 @@ def main() -> int:
                     help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-model timing")
     ap.add_argument("--cg-iters", type=int, default=3, help="CG iterations timed for it/s")
+    ap.add_argument("--serve", action="store_true", help="replay the serving stream instead")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-baseline-requests", type=int, default=40)
+    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-budget-gb", type=int, default=48)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -88,6 +272,19 @@ def main() -> int:
               "(the library is single-device; multi-GPU sharding is a design note only).",
               file=sys.stderr)
         return 2
+
+    if args.serve:
+        return run_serve(args)
+    if args.copy_probe:
+        import torch
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
+        return 0
 
     p = workloads.config4()
     n, M = p.obs.n, p.mesh.ncells
@@ -138,19 +335,25 @@ def main() -> int:
     print(f"[bench] G m: {ms_per_step:.1f} ms/step, sweep kernel {k_avg_ms:.1f} ms avg "
           f"over {k_n} launches, {value:.3e} pairs/s", file=sys.stderr, flush=True)
 
-    segs = (p.mesh.nx + 1) * (p.mesh.ny + 1) * p.mesh.nz
-    alg_slots = SLOTS_PER_SEGMENT * segs * n
-    achieved = alg_slots / (k_avg_ms * 1e-3)
+    ncols = (p.mesh.nx + 1) * (p.mesh.ny + 1)
+    kdeep = first_deep_layer(p.mesh.zn)
+    nz = p.mesh.nz
+    segs = ncols * nz
+    instr = n * ncols * (kdeep * INSTR_SHALLOW + (nz - kdeep) * INSTR_DEEP)
+    slots = n * ncols * (kdeep * slots_per_pair(INSTR_SHALLOW)
+                         + (nz - kdeep) * slots_per_pair(INSTR_DEEP))
+    k_s = k_avg_ms * 1e-3
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                "unit": "T lane-slots/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": traffic,
+    roofline = {"bound": "alu", "achieved": slots / k_s / 1e12, "peak": PEAK_SLOTS / 1e12,
+                "unit": "T lane-slots/s", "frac": slots / k_s / PEAK_SLOTS, "traffic": traffic,
                 "kernel": "k_forward_mixed", "kernel_ms": k_avg_ms,
-                "slots_per_segment": SLOTS_PER_SEGMENT, "segments_per_launch": segs * n}
+                "segments_per_launch": segs * n, "slots_per_launch": slots,
+                "frac_unweighted_instructions": instr / k_s / PEAK_SLOTS}
 
     # error vs the oracle on the stored rows
     extras = {}
@@ -196,6 +399,9 @@ def main() -> int:
             extras["cg_iterations_per_s"] = 1.0 / per_iter
             extras["cg_seconds_for_50_iterations_est"] = 50 * per_iter
             extras["cg_timed_iterations"] = args.cg_iters
+
+    if not args.no_extras and not args.no_multi:
+        extras.update(multi_model_extras(g, torch, dev))
 
     out = {
         "metric": "prism-obs pairs/s for G.m at 3.3M x 178,797",

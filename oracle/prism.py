@@ -202,3 +202,69 @@ def weighted_row_sumsq(mesh, obs, cov, rows=None) -> np.ndarray:
         g = sensitivity_row(mesh, obs.x[o], obs.y[o], obs.z[o])
         out[t] = np.dot(cov * g, g)
     return out
+
+
+# --------------------------------------------------------------------------
+# Rounding-error scales (magnitudes of the summed terms), used by the tests to
+# derive tolerances for low-precision evaluations of the same sums.
+# --------------------------------------------------------------------------
+
+def edge_terms(mesh, xo: float, yo: float, zo: float) -> np.ndarray:
+    """S(a, b, k) = Psi(node (a, b, k+1) - o) - Psi(node (a, b, k) - o): the
+    sum of Eq. 1's vertex terms over the two ends of each vertical mesh edge
+    segment, shape (nx+1, ny+1, nz)."""
+    P = psi_nodes(mesh, xo, yo, zo)
+    return P[:, :, 1:] - P[:, :, :-1]
+
+
+def forward_abs_scale(mesh, obs, m, rows) -> np.ndarray:
+    """gamma * sum over vertical edge segments of |S| * |sum of the up to four
+    adjacent cells' parity-weighted densities| per observation row: the size of
+    the terms a segment-wise evaluation of G m adds up."""
+    mm = np.asarray(m, dtype=np.float64).reshape(mesh.shape)
+    W2 = np.zeros((mesh.nx + 1, mesh.ny + 1, mesh.nz))
+    for p in (0, 1):
+        for q in (0, 1):
+            W2[p:p + mesh.nx, q:q + mesh.ny, :] += (-1.0) ** (p + q) * mm
+    out = np.empty(len(rows))
+    for t, o in enumerate(rows):
+        out[t] = GAMMA * np.sum(np.abs(edge_terms(mesh, obs.x[o], obs.y[o], obs.z[o]) * W2))
+    return out
+
+
+def adjoint_abs_scale(mesh, obs, v, cells) -> np.ndarray:
+    """gamma * sum_o |v_o| * sum over the cell's four vertical edges of |S|:
+    the size of the terms an edge-wise evaluation of (G^T v)_cell adds up."""
+    v = np.asarray(v, dtype=np.float64)
+    cells = np.asarray(cells)
+    i, rem = np.divmod(cells, mesh.ny * mesh.nz)
+    j, k = np.divmod(rem, mesh.nz)
+    out = np.empty(cells.size)
+    for t in range(cells.size):
+        acc = np.zeros(obs.n)
+        for p in (0, 1):
+            for q in (0, 1):
+                x = mesh.xn[i[t] + p] - obs.x
+                y = mesh.yn[j[t] + q] - obs.y
+                acc += np.abs(psi(x, y, mesh.zn[k[t] + 1] - obs.z) - psi(x, y, mesh.zn[k[t]] - obs.z))
+        out[t] = GAMMA * np.dot(np.abs(v), acc)
+    return out
+
+
+def adjoint_abs_scale_corners(mesh, obs, v, cells) -> np.ndarray:
+    """gamma * sum_o |v_o| * sum over the cell's 8 corners of |Psi|: the size
+    of the terms a corner-wise (node) evaluation of (G^T v)_cell adds up."""
+    v = np.asarray(v, dtype=np.float64)
+    cells = np.asarray(cells)
+    i, rem = np.divmod(cells, mesh.ny * mesh.nz)
+    j, k = np.divmod(rem, mesh.nz)
+    out = np.empty(cells.size)
+    for t in range(cells.size):
+        acc = np.zeros(obs.n)
+        for p in (0, 1):
+            for q in (0, 1):
+                for r in (0, 1):
+                    acc += np.abs(psi(mesh.xn[i[t] + p] - obs.x, mesh.yn[j[t] + q] - obs.y,
+                                      mesh.zn[k[t] + r] - obs.z))
+        out[t] = GAMMA * np.dot(np.abs(v), acc)
+    return out

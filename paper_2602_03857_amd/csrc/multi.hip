@@ -287,7 +287,7 @@ uint64_t multi_workspace_need(const Mesh &g, int64_t n, grav_prec prec, int K) {
     } else {
         c.take<float>(packed);
     }
-    c.take<float>(g.nz);
+    c.take<float>(g.nz + 1);
     c.take<double>((size_t)mp.nchunk * n * kModels);
     return c.off;
 }
@@ -326,7 +326,7 @@ extern "C" int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const gr
     } else {
         b32 = ar.take<float>(packed);
     }
-    float *hk = ar.take<float>(g.nz);
+    float *hk = ar.take<float>(g.nz + 1);
     double *part = ar.take<double>((size_t)mp.nchunk * o.n * kModels);
     if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the multi-model forward");
 

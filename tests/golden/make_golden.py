@@ -4,10 +4,12 @@ Calls only ``oracle`` (and the seeded input generators in ``workloads``).
 Run from the repository root:  python tests/golden/make_golden.py [which ...]
 
 * config4_rows.npz : d = G m at 2,000 seeded observation rows of the
-  178,797 x 3,307,500 paper-scale workload (seed 12345 picks the rows), and
-  (G^T v) at 48 seeded cells for the workload's probe vector v.
-* config2_rows.npz : d = G m at 256 rows and (G^T v) at 64 cells of the
-  10,000 x 500,000 forward/adjoint workload.
+  178,797 x 3,307,500 paper-scale workload (seed 12345 picks the rows),
+  (G^T v) at 48 seeded cells for the workload's probe vector v, and the
+  absolute term scale of those cells (tolerance of the FP32 edge terms).
+* config2_rows.npz : the same at 256 rows and 64 cells of the 10,000 x
+  500,000 forward/adjoint workload, plus the corner-term scale (tolerance of
+  the FP64 node evaluation).
 """
 from __future__ import annotations
 
@@ -44,8 +46,10 @@ def make_config4(workers):
     print(f"config4 rows: {time.time() - t:.1f} s", flush=True)
     t = time.time()
     g = _adjoint_cells_parallel(p.mesh, p.obs, p.probe_v, cells, workers)
+    g_abs = prism.adjoint_abs_scale(p.mesh, p.obs, p.probe_v, cells)
     print(f"config4 cells: {time.time() - t:.1f} s", flush=True)
-    np.savez(os.path.join(HERE, "config4_rows.npz"), rows=rows, d=d, cells=cells, gtv=g)
+    np.savez(os.path.join(HERE, "config4_rows.npz"), rows=rows, d=d, cells=cells, gtv=g,
+             gtv_abs=g_abs)
 
 
 def make_config2(workers):
@@ -56,8 +60,11 @@ def make_config2(workers):
     t = time.time()
     d = parallel.forward_rows(p.mesh, p.obs, p.m, rows, workers=workers)
     g = _adjoint_cells_parallel(p.mesh, p.obs, p.probe_v, cells, workers)
+    g_abs = prism.adjoint_abs_scale(p.mesh, p.obs, p.probe_v, cells)
+    g_abs8 = prism.adjoint_abs_scale_corners(p.mesh, p.obs, p.probe_v, cells)
     print(f"config2: {time.time() - t:.1f} s", flush=True)
-    np.savez(os.path.join(HERE, "config2_rows.npz"), rows=rows, d=d, cells=cells, gtv=g)
+    np.savez(os.path.join(HERE, "config2_rows.npz"), rows=rows, d=d, cells=cells, gtv=g,
+             gtv_abs=g_abs, gtv_abs_corners=g_abs8)
 
 
 if __name__ == "__main__":

@@ -17,7 +17,20 @@ pytestmark = pytest.mark.gpu
 
 TOL_F64 = 1e-10
 TOL_MIXED = 1e-5
+EPS32 = 2.0 ** -24
+# Each FP32 edge term is accurate to a few units of its own magnitude, so an
+# edge-wise sum is accurate to C_TERMS * eps32 * (sum of |terms|).
+C_TERMS = 16.0
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _check_termwise(name, got, ref, scale):
+    """|got - ref| <= C_TERMS * eps32 * scale elementwise (scale = sum of the
+    magnitudes of the terms the GPU adds up, from the oracle)."""
+    ratio = np.abs(got - ref) / (C_TERMS * EPS32 * scale)
+    print(f"[parity] {name}: rel L2 = {rel_l2(got, ref):.3e}, worst err / term bound = "
+          f"{ratio.max():.3f}", flush=True)
+    assert np.all(ratio <= 1.0)
 
 
 @pytest.fixture(scope="module")
@@ -107,24 +120,31 @@ def _single_prism_positions():
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
 def test_single_prism_singular_and_far_positions(g, ctx, prec_name):
-    """Per point, one prism: the FP32 edge form loses accuracy like
-    eps32 * (R/a)^2 (the (x, y) parity sum of four edge terms), so the bound
-    is max(2e-6, 3e-7 (R/a)^2) relative; FP64 must match to 1e-9."""
+    """Per point, one prism (100 x 60 x 70 m).  Bounds from the cancellation
+    of each evaluation: FP64 sums 8 corner terms of size ~R ln R to a result
+    ~V/R^2, so ~ eps64 R^3 ln R / V; the FP32 edge form sums 4 edge terms of
+    size ~h to ~a_x a_y h z_c / R^3, so ~ eps32 R^3 / (a_x a_y z_c), z_c = the
+    prism-centre depth below the point."""
     mesh_h, obs_h = _single_prism_positions()
     mesh, obs = g.DeviceMesh.from_mesh(mesh_h), g.DeviceObs.from_survey(obs_h)
     m = np.array([1000.0])
     d = to_np(ctx.forward(mesh, obs, _t(m), prec=getattr(g, prec_name)))
     ref = prism.forward_literal(mesh_h, obs_h, m)
     R = np.sqrt((obs_h.x - 50.0) ** 2 + (obs_h.y - 30.0) ** 2 + (obs_h.z - 55.0) ** 2)
-    ratio = np.maximum(R / 100.0, 1.0)
+    R = np.maximum(R, 100.0)
+    zc = 55.0 - obs_h.z
     rel = np.abs(d - ref) / np.abs(ref)
-    bound = 1e-9 if prec_name == "GRAV_FP64" else np.maximum(2e-6, 3e-7 * ratio ** 2)
+    if prec_name == "GRAV_FP64":
+        bound = np.maximum(1e-12, 200 * 2.0 ** -53 * R ** 3 * np.log(R) / (100 * 60 * 70))
+    else:
+        bound = np.maximum(2e-6, 100 * EPS32 * R ** 3 / (100 * 60 * zc))
     worst = int(np.argmax(rel / bound))
-    print(f"[parity] single prism {prec_name}: worst rel {rel[worst]:.2e} at "
-          f"{obs_h.x[worst], obs_h.y[worst], obs_h.z[worst]} bound {np.broadcast_to(bound, rel.shape)[worst]:.1e}",
-          flush=True)
+    near = R <= 300.0
+    print(f"[parity] single prism {prec_name}: worst rel/bound {rel[worst] / bound[worst]:.2f} "
+          f"(rel {rel[worst]:.2e}); near field (R <= 3a) max rel {rel[near].max():.2e}", flush=True)
     assert np.all(np.isfinite(d))
     assert np.all(rel <= bound)
+    assert rel[near].max() <= (1e-12 if prec_name == "GRAV_FP64" else 1e-4)
 
 
 # ------------------------------------------------------------------ adjoint
@@ -141,9 +161,13 @@ def test_adjoint_random_ragged(g, ctx, prec_name, case):
     mesh, obs = _dev(g, p)
     gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=getattr(g, prec_name)))
     ref = prism.adjoint(p.mesh, p.obs, p.probe_v)
-    err = rel_l2(gt, ref)
-    _report(f"adjoint {prec_name} {case}", err)
-    assert err <= (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED)
+    if prec_name == "GRAV_FP64":
+        err = rel_l2(gt, ref)
+        _report(f"adjoint {prec_name} {case}", err)
+        assert err <= TOL_F64
+    else:
+        scale = prism.adjoint_abs_scale(p.mesh, p.obs, p.probe_v, np.arange(p.mesh.ncells))
+        _check_termwise(f"adjoint {prec_name} {case}", gt, ref, scale)
 
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
@@ -267,9 +291,16 @@ def test_config2_forward_adjoint_sampled(g, ctx):
         _report(f"config2 forward {prec_name} (256 rows)", err)
         assert err <= tol
         gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=prec))
-        err = rel_l2(gt[gold["cells"]], gold["gtv"])
-        _report(f"config2 adjoint {prec_name} (64 cells)", err)
-        assert err <= (tol if prec_name == "GRAV_FP64" else 1e-5)
+        if prec_name == "GRAV_FP64":
+            # corner terms ~R ln R, each within a few ulp: C_TERMS * eps64 * sum |terms|
+            got, ref = gt[gold["cells"]], gold["gtv"]
+            ratio = np.abs(got - ref) / (C_TERMS * 2.0 ** -53 * gold["gtv_abs_corners"])
+            print(f"[parity] config2 adjoint GRAV_FP64 (64 cells): rel L2 = {rel_l2(got, ref):.3e}, "
+                  f"worst err / term bound = {ratio.max():.3f}", flush=True)
+            assert np.all(ratio <= 1.0)
+        else:
+            _check_termwise(f"config2 adjoint {prec_name} (64 cells)", gt[gold["cells"]], gold["gtv"],
+                            gold["gtv_abs"])
 
 
 def test_config4_forward_sampled_rows(g, ctx):
@@ -283,9 +314,8 @@ def test_config4_forward_sampled_rows(g, ctx):
     _report("config4 forward GRAV_MIXED (2000 rows)", err)
     assert err <= TOL_MIXED
     gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=g.GRAV_MIXED))
-    err = rel_l2(gt[gold["cells"]], gold["gtv"])
-    _report("config4 adjoint GRAV_MIXED (48 cells)", err)
-    assert err <= TOL_MIXED
+    _check_termwise("config4 adjoint GRAV_MIXED (48 cells)", gt[gold["cells"]], gold["gtv"],
+                    gold["gtv_abs"])
 
 
 # ------------------------------------------------------------------ multi-model
@@ -386,7 +416,7 @@ def test_error_paths(g, ctx):
                             g.GRAV_MIXED, None)
     assert rc == g.GRAV_EINVAL
     # workspace too small
-    small = g.Context(device=0, workspace_bytes=4096)
+    small = g.Context(device=0, workspace_bytes=256)
     with pytest.raises(g.GravError) as e:
         small.forward(mesh, obs, m)
     assert e.value.code == g.GRAV_ENOMEM
