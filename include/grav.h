@@ -164,6 +164,10 @@ typedef struct {
     double tol;          /* stop when ||delta_d - A y||_2 / ||delta_d||_2 <= tol (recursive residual) */
     int32_t max_iter;    /* iteration cap (>= 1) */
     int32_t fixed_iters; /* > 0: run exactly this many iterations, no residual checks */
+    int32_t precond;     /* 0: plain CG; 1: Jacobi-preconditioned CG with
+                            M = diag(G C G^T) + lambda I (the trace sweep's
+                            per-observation terms; grav_invert only, the
+                            server requires 0) */
 } grav_cg_opts;
 
 typedef struct {

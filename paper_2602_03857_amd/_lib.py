@@ -31,7 +31,7 @@ class CtxOpts(ctypes.Structure):
 
 class CgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("fixed_iters", ctypes.c_int32)]
+                ("fixed_iters", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class CgInfo(ctypes.Structure):

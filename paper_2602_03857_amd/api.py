@@ -191,7 +191,7 @@ class Context:
 
     def invert(self, mesh, obs, d_obs, wdepth, lam=-1.0, m_ref=None, tol=1e-6, max_iter=200,
                fixed_iters=0, m_out=None, d_pred=None, want_pred=False, prec=GRAV_MIXED,
-               stream=None):
+               stream=None, precond=0):
         """Data-space CG inversion (Eq. 11).  Returns (m, d_pred or None, info dict)."""
         _check(d_obs, torch.float64, obs.n, "d_obs", self.device)
         _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
@@ -204,7 +204,7 @@ class Context:
             d_pred = torch.empty(obs.n, dtype=torch.float64, device=self.device)
         if d_pred is not None:
             _check(d_pred, torch.float64, obs.n, "d_pred", self.device)
-        cg = CgOpts(float(tol), int(max_iter), int(fixed_iters))
+        cg = CgOpts(float(tol), int(max_iter), int(fixed_iters), int(precond))
         info = CgInfo()
         rc = lib.grav_invert(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c), d_obs.data_ptr(),
                              wdepth.data_ptr(), float(lam),

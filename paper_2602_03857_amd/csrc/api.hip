@@ -370,6 +370,8 @@ extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs 
     if (!std::isfinite(lambda)) return fail(ctx, GRAV_EINVAL, "lambda must be finite");
     if (cg->fixed_iters <= 0 && (cg->max_iter < 1 || !(cg->tol >= 0.0)))
         return fail(ctx, GRAV_EINVAL, "CG needs max_iter >= 1 and tol >= 0, or fixed_iters > 0");
+    if (cg->precond != 0 && cg->precond != 1)
+        return fail(ctx, GRAV_EINVAL, "precond must be 0 (none) or 1 (Jacobi)");
     if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
     const Mesh g = to_mesh(mesh);
     const Obs o = to_obs(obs);

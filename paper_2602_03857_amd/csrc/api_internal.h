@@ -28,11 +28,14 @@ struct grav_ctx {
 namespace grav {
 
 // Reserved head of the workspace: [0,256) flags, [256,512) scalars,
-// [512, 512 + 8*kDotBlocks) dot partials.
+// [512, 512 + 16*kDotBlocks) two arrays of dot partials.
 constexpr size_t kReserveBytes = 16384;
 
 inline double *ctx_scalars(grav_ctx *ctx) { return reinterpret_cast<double *>(ctx->ws + 256); }
 inline double *ctx_dot_partials(grav_ctx *ctx) { return reinterpret_cast<double *>(ctx->ws + 512); }
+inline double *ctx_dot_partials2(grav_ctx *ctx) {
+    return reinterpret_cast<double *>(ctx->ws + 512 + 8 * kDotBlocks);
+}
 
 struct ArrayCheck {
     const double *ptr;

@@ -123,13 +123,26 @@ hipError_t launch_validate_finite(const double *w, int64_t len, int *flags, hipS
 
 // ---- vector kernels for CG ------------------------------------------------
 constexpr int kDotBlocks = 512;
-enum : int { kRR = 0, kPQ = 1, kRRNew = 2, kB2 = 3, kAlpha = 4, kBeta = 5, kNumScalars = 8 };
-enum : int { kFinishInit = 0, kFinishPQ = 1, kFinishRRNew = 2, kFinishPlain = 3 };
+enum : int { kRR = 0, kPQ = 1, kRRNew = 2, kB2 = 3, kAlpha = 4, kBeta = 5, kRZ = 6, kNumScalars = 8 };
+enum : int {
+    kFinishInit = 0, kFinishPQ = 1, kFinishRRNew = 2, kFinishPlain = 3,
+    kFinishPQPrecond = 4,   // alpha = (r.z) / (p.Ap)
+    kFinishRZNew = 5        // beta = (r'.z') / (r.z), then r.z <- r'.z'
+};
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *partials, hipStream_t st);
 hipError_t launch_dot_finish(const double *partials, double *scal, int mode, int slot, hipStream_t st);
 // y += alpha p ; r -= alpha q ; partial (r . r) into partials
 hipError_t launch_cg_update_yr(double *y, double *r, const double *p, const double *q, int64_t n,
                                const double *scal, double *partials, hipStream_t st);
+// Jacobi-preconditioned CG: dinv = 1 / (diag + lambda); z = dinv r, p = z,
+// partial r.r and r.z (first iterate)
+hipError_t launch_pcg_setup(const double *diag, double lambda, double *dinv, const double *r,
+                            double *z, double *p, int64_t n, double *part_rr, double *part_rz,
+                            hipStream_t st);
+// y += alpha p ; r -= alpha q ; z = dinv r ; partial r.r and r.z
+hipError_t launch_pcg_update_yrz(double *y, double *r, double *z, const double *p, const double *q,
+                                 const double *dinv, int64_t n, const double *scal,
+                                 double *part_rr, double *part_rz, hipStream_t st);
 // p = r + beta p
 hipError_t launch_cg_update_p(double *p, const double *r, int64_t n, const double *scal,
                               hipStream_t st);

@@ -32,28 +32,38 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
     double *r = ar.take<double>(n);
     double *p = ar.take<double>(n);
     double *q = ar.take<double>(n);
+    const bool pc = cg.precond == 1;            // Jacobi preconditioner
+    double *z = pc ? ar.take<double>(n) : nullptr;
+    double *dinv = pc ? ar.take<double>(n) : nullptr;
     if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the CG vectors");
     double *scal = ctx_scalars(ctx);
     double *dpart = ctx_dot_partials(ctx);
+    double *dpart2 = ctx_dot_partials2(ctx);
 
     double trace = 0.0;
-    if (lambda < 0.0) {   // lambda = 1e-2 * trace(G C G^T) / n
-        int rc = op_trace(ctx, ar, g, o, wdepth, &trace, nullptr, prec, st);
+    if (lambda < 0.0 || pc) {   // lambda = 1e-2 * trace(G C G^T) / n; diag(G C G^T) for M
+        int rc = op_trace(ctx, ar, g, o, wdepth, &trace, dinv, prec, st);
         if (rc) return rc;
-        lambda = 1e-2 * trace / (double)n;
+        if (lambda < 0.0) lambda = 1e-2 * trace / (double)n;
     }
 
-    // r = delta_d = d_obs - G m_ref ; p = r ; y = 0
+    // r = delta_d = d_obs - G m_ref ; p = r (or M^-1 r) ; y = 0
     if (m_ref) {
         int rc = op_forward(ctx, ar, g, o, m_ref, r, prec, st, -GRAV_GAMMA, d_obs, 1.0);
         if (rc) return rc;
     } else {
         HIP_TRY(launch_sub(d_obs, nullptr, r, n, st), "copy");
     }
-    HIP_TRY(launch_sub(r, nullptr, p, n, st), "copy");
     HIP_TRY(launch_fill(y, 0.0, n, st), "fill");
-    HIP_TRY(launch_dot(r, r, n, dpart, st), "dot");
-    HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+    if (pc) {
+        HIP_TRY(launch_pcg_setup(dinv, lambda, dinv, r, z, p, n, dpart, dpart2, st), "pcg setup");
+        HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+        HIP_TRY(launch_dot_finish(dpart2, scal, kFinishPlain, kRZ, st), "dot");
+    } else {
+        HIP_TRY(launch_sub(r, nullptr, p, n, st), "copy");
+        HIP_TRY(launch_dot(r, r, n, dpart, st), "dot");
+        HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+    }
     int rc = read_scalars(ctx, st);
     if (rc) return rc;
     const double b2 = ctx->h_scal[kB2];
@@ -67,9 +77,16 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
         rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
         if (rc) return rc;
         HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
-        HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQ, 0, st), "dot");
-        HIP_TRY(launch_cg_update_yr(y, r, p, q, n, scal, dpart, st), "cg update");
-        HIP_TRY(launch_dot_finish(dpart, scal, kFinishRRNew, 0, st), "dot");
+        if (pc) {
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQPrecond, 0, st), "dot");
+            HIP_TRY(launch_pcg_update_yrz(y, r, z, p, q, dinv, n, scal, dpart, dpart2, st), "pcg update");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kRR, st), "dot");
+            HIP_TRY(launch_dot_finish(dpart2, scal, kFinishRZNew, 0, st), "dot");
+        } else {
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQ, 0, st), "dot");
+            HIP_TRY(launch_cg_update_yr(y, r, p, q, n, scal, dpart, st), "cg update");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishRRNew, 0, st), "dot");
+        }
         ++it;
         if (!fixed) {
             rc = read_scalars(ctx, st);
@@ -77,7 +94,7 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
             relres = std::sqrt(ctx->h_scal[kRR] / b2);
             if (relres <= cg.tol) { converged = true; break; }
         }
-        HIP_TRY(launch_cg_update_p(p, r, n, scal, st), "cg update");
+        HIP_TRY(launch_cg_update_p(p, pc ? z : r, n, scal, st), "cg update");
     }
     if (fixed && b2 > 0.0) {
         rc = read_scalars(ctx, st);
@@ -165,7 +182,7 @@ uint64_t workspace_need(int nx, int ny, int nz, int64_t n, grav_op op, grav_prec
             return need_trace(g, n);
         case GRAV_OP_INVERT: {
             Counter c;
-            for (int i = 0; i < 4; ++i) c.take<double>(n);
+            for (int i = 0; i < 6; ++i) c.take<double>(n);
             size_t inner = need_dataspace(g, n, prec);
             const size_t t = need_trace(g, n);
             if (t > inner) inner = t;

@@ -51,7 +51,9 @@ __device__ __forceinline__ void forward_mixed_block(
 }
 
 // One observation's contribution to a lane's layer chunk of the adjoint.
-template <bool kDeep>
+// kFull: the chunk has exactly kAdjLayers layers (no per-layer guard, so the
+// segments form one basic block the compiler can interleave).
+template <bool kDeep, bool kFull>
 __device__ __forceinline__ void adjoint_obs(double X, double Y, const double *__restrict__ zn, int k0,
                                             int cnt, const float (&h)[kAdjLayers], double xo,
                                             double yo, double zo, double vo,
@@ -60,7 +62,7 @@ __device__ __forceinline__ void adjoint_obs(double X, double Y, const double *__
     Node top = make_node(c, static_cast<float>(zn[k0] - zo));
 #pragma unroll
     for (int j = 0; j < kAdjLayers; ++j) {
-        if (j < cnt) {
+        if (kFull || j < cnt) {
             const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
             const float S = edge_segment<kDeep>(c, top, bot, h[j]);
             acc[j] = fma(vo, static_cast<double>(S), acc[j]);
@@ -70,7 +72,8 @@ __device__ __forceinline__ void adjoint_obs(double X, double Y, const double *__
 }
 
 // Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane, layer
-// chunk kc (of nkc, <= kAdjLayers layers), observations of part `part`;
+// chunk kc (layers kc*kAdjLayers ..., the last chunk may be shorter),
+// observations of part `part`;
 // writes upart[part][segment] = sum_{o in part} v_o S (FP64, one register
 // pair per layer, no cross-lane reduction).
 __device__ __forceinline__ void adjoint_mixed_block(
@@ -84,8 +87,8 @@ __device__ __forceinline__ void adjoint_mixed_block(
     const int a = (int)(colc / ny1);
     const int b = (int)(colc - (int64_t)a * ny1);
     const double X = xn[a], Y = yn[b];
-    const int k0 = (int)((int64_t)kc * nz / nkc);
-    const int cnt = (int)((int64_t)(kc + 1) * nz / nkc) - k0;
+    const int k0 = kc * kAdjLayers;
+    const int cnt = nz - k0 < kAdjLayers ? nz - k0 : kAdjLayers;
     float h[kAdjLayers];
 #pragma unroll
     for (int j = 0; j < kAdjLayers; ++j) h[j] = j < cnt ? hk[k0 + j] : 1.0f;
@@ -95,12 +98,22 @@ __device__ __forceinline__ void adjoint_mixed_block(
     const int64_t o0 = (int64_t)part * obs_per_part;
     const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
     const bool deep = k0 >= reinterpret_cast<const int *>(hk + nz)[0];   // uniform per block
-    if (deep) {
-        for (int64_t o = o0; o < o1; ++o)
-            adjoint_obs<true>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+    if (cnt == kAdjLayers) {
+        if (deep) {
+            for (int64_t o = o0; o < o1; ++o)
+                adjoint_obs<true, true>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+        } else {
+            for (int64_t o = o0; o < o1; ++o)
+                adjoint_obs<false, true>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+        }
     } else {
-        for (int64_t o = o0; o < o1; ++o)
-            adjoint_obs<false>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+        if (deep) {
+            for (int64_t o = o0; o < o1; ++o)
+                adjoint_obs<true, false>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+        } else {
+            for (int64_t o = o0; o < o1; ++o)
+                adjoint_obs<false, false>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
+        }
     }
     if (col < ncols) {
         double *__restrict__ dst = upart + (int64_t)part * ncols * nz + col * nz + k0;

@@ -56,6 +56,14 @@ __global__ __launch_bounds__(256) void k_dot_finish(const double *__restrict__ p
                 scal[kBeta] = scal[kRR] > 0.0 ? s / scal[kRR] : 0.0;
                 scal[kRR] = s;
                 break;
+            case kFinishPQPrecond:
+                scal[kPQ] = s;
+                scal[kAlpha] = s > 0.0 ? scal[kRZ] / s : 0.0;
+                break;
+            case kFinishRZNew:
+                scal[kBeta] = scal[kRZ] > 0.0 ? s / scal[kRZ] : 0.0;
+                scal[kRZ] = s;
+                break;
             default:
                 scal[slot] = s;
                 break;
@@ -78,6 +86,59 @@ __global__ __launch_bounds__(256) void k_cg_update_yr(double *__restrict__ y, do
     }
     const double s = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_pcg_setup(const double *__restrict__ diag, double lambda,
+                                                   double *__restrict__ dinv,
+                                                   const double *__restrict__ r,
+                                                   double *__restrict__ z, double *__restrict__ p,
+                                                   int64_t n, double *__restrict__ part_rr,
+                                                   double *__restrict__ part_rz) {
+    double arr = 0.0, arz = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kDotBlocks * 256) {
+        const double di = 1.0 / (diag[i] + lambda);
+        dinv[i] = di;
+        const double ri = r[i], zi = di * ri;
+        z[i] = zi;
+        p[i] = zi;
+        arr = fma(ri, ri, arr);
+        arz = fma(ri, zi, arz);
+    }
+    const double s1 = block_sum(arr);
+    __syncthreads();
+    const double s2 = block_sum(arz);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = s1;
+        part_rz[blockIdx.x] = s2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pcg_update_yrz(double *__restrict__ y, double *__restrict__ r,
+                                                        double *__restrict__ z,
+                                                        const double *__restrict__ p,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ dinv, int64_t n,
+                                                        const double *__restrict__ scal,
+                                                        double *__restrict__ part_rr,
+                                                        double *__restrict__ part_rz) {
+    const double alpha = scal[kAlpha];
+    double arr = 0.0, arz = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kDotBlocks * 256) {
+        y[i] = fma(alpha, p[i], y[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        const double zi = dinv[i] * ri;
+        z[i] = zi;
+        arr = fma(ri, ri, arr);
+        arz = fma(ri, zi, arz);
+    }
+    const double s1 = block_sum(arr);
+    __syncthreads();
+    const double s2 = block_sum(arz);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = s1;
+        part_rz[blockIdx.x] = s2;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_cg_update_p(double *__restrict__ p,
@@ -126,6 +187,20 @@ hipError_t launch_dot_finish(const double *partials, double *scal, int mode, int
 hipError_t launch_cg_update_yr(double *y, double *r, const double *p, const double *q, int64_t n,
                                const double *scal, double *partials, hipStream_t st) {
     k_cg_update_yr<<<kDotBlocks, 256, 0, st>>>(y, r, p, q, n, scal, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_setup(const double *diag, double lambda, double *dinv, const double *r,
+                            double *z, double *p, int64_t n, double *part_rr, double *part_rz,
+                            hipStream_t st) {
+    k_pcg_setup<<<kDotBlocks, 256, 0, st>>>(diag, lambda, dinv, r, z, p, n, part_rr, part_rz);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update_yrz(double *y, double *r, double *z, const double *p, const double *q,
+                                 const double *dinv, int64_t n, const double *scal,
+                                 double *part_rr, double *part_rz, hipStream_t st) {
+    k_pcg_update_yrz<<<kDotBlocks, 256, 0, st>>>(y, r, z, p, q, dinv, n, scal, part_rr, part_rz);
     return hipGetLastError();
 }
 

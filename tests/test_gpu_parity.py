@@ -247,6 +247,25 @@ def test_invert_config1_vs_cholesky(g, ctx, config1_ref, prec_name):
     assert rel_l2(to_np(d_pred), G @ m_chol) <= 1e-4
 
 
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_invert_jacobi_preconditioned(g, ctx, config1_ref, prec_name):
+    """Jacobi-preconditioned CG (M = diag(G C G^T) + lambda I) reaches the same
+    unique solution of Eq. 11 as the Cholesky solve."""
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    prec = getattr(g, prec_name)
+    _, _, plain = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=p.cg_tol,
+                             max_iter=2000, prec=prec)
+    m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=p.cg_tol,
+                            max_iter=2000, prec=prec, precond=1)
+    print(f"[parity] invert config1 {prec_name} Jacobi: {info['iters']} iterations "
+          f"(plain CG {plain['iters']})", flush=True)
+    assert info["converged"] and info["relres"] <= p.cg_tol
+    err = rel_l2(to_np(m), m_chol)
+    _report(f"invert config1 {prec_name} Jacobi density", err)
+    assert err <= 1e-4
+
+
 def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
     p, G, d_obs, trace, lam, m_chol = config1_ref
     mesh, obs = _dev(g, p)
