@@ -16,7 +16,8 @@
 //      (FP32 accumulation), B = the models pre-split into bf16 hi/lo and
 //      packed so that each lane loads its 8 operands with one 16-byte load.
 // After each prism-column block the FP32 MFMA accumulators are added into
-// FP64 registers, so FP32 accumulates at most 16 nz terms.  The GRAV_FP32_VALU
+// per-thread FP64 accumulators kept in LDS, so FP32 accumulates at most 16 nz
+// terms.  The GRAV_FP32_VALU
 // variant keeps steps 1-2 (G in FP32) and contracts on the vector ALUs.
 #include <hip/hip_runtime.h>
 
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     __shared__ __attribute__((aligned(16))) __bf16 sAlo[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sA32[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sB32[kPrismsPerStep][kModels];
+    __shared__ double sAcc[16][256];    // per-thread FP64 accumulators (column t)
 
     const int chunk = (int)(blockIdx.x % nchunk);
     const int64_t tile = blockIdx.x / nchunk;
@@ -110,18 +112,17 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     const int r0 = 32 * (wv & 1), c0 = 32 * (wv >> 1);
     f32x16 acc;
     float acc32[16];
-    double acc64[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         acc[v] = 0.0f;
         acc32[v] = 0.0f;
-        acc64[v] = 0.0;
+        sAcc[v][t] = 0.0;
     }
 
     for (int64_t blk = b0; blk < b1; ++blk) {
         const int i0 = (int)(blk / nby) * kPB;
         const int j0 = (int)(blk % nby) * kPB;
-        float cx[kColsPerWave], cy[kColsPerWave], cR[kColsPerWave], czR[kColsPerWave];
+        float cx[kColsPerWave], cy[kColsPerWave], cR[kColsPerWave];
         bool valid[kColsPerWave];
 #pragma unroll
         for (int u = 0; u < kColsPerWave; ++u) {
@@ -132,9 +133,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             cx[u] = column_offset(xn[ac], xo);
             cy[u] = column_offset(yn[bc], yo);
             const Column col = column_from_xy(cx[u], cy[u]);
-            const Node top = make_node(col, ztop);
-            cR[u] = top.R;
-            czR[u] = top.zR;
+            cR[u] = make_node(col, ztop).R;
         }
         float zt = ztop, zzt = ztop * ztop;
         for (int k = 0; k < nz; ++k) {
@@ -145,17 +144,20 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             for (int u = 0; u < kColsPerWave; ++u) {
                 const int c = wv + 4 * u;
                 if (c < kEdgeCols) {
-                    const Column col = column_from_xy(cx[u], cy[u]);
+                    // recompute the column terms each layer rather than keeping
+                    // those of all seven columns live across the layer loop
+                    float xu = cx[u], yu = cy[u];
+                    asm volatile("" : "+v"(xu), "+v"(yu));
+                    const Column col = column_from_xy(xu, yu);
                     Node top;
                     top.z = zt;
                     top.zz = zzt;
                     top.R = cR[u];
-                    top.zR = czR[u];
+                    top.zR = zt * cR[u];
                     const Node bot = make_node(col, zb);
                     const float S = edge_segment(col, top, bot, h);
                     sS[c][lo_] = valid[u] ? S : 0.0f;
                     cR[u] = bot.R;
-                    czR[u] = bot.zR;
                 }
             }
             zt = zb;
@@ -205,10 +207,10 @@ __global__ __launch_bounds__(256) void k_forward_multi(
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             if (kMfma) {
-                acc64[v] += static_cast<double>(acc[v]);
+                sAcc[v][t] += static_cast<double>(acc[v]);
                 acc[v] = 0.0f;
             } else {
-                acc64[v] += static_cast<double>(acc32[v]);
+                sAcc[v][t] += static_cast<double>(acc32[v]);
                 acc32[v] = 0.0f;
             }
         }
@@ -220,11 +222,11 @@ __global__ __launch_bounds__(256) void k_forward_multi(
         for (int v = 0; v < 16; ++v) {
             const int row = r0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
             const int64_t og = tile * kTileObs + row;
-            if (og < n) partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] = acc64[v];
+            if (og < n) partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] = sAcc[v][t];
         }
     } else if (o < n) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = acc64[v];
+        for (int v = 0; v < 16; ++v) partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = sAcc[v][t];
     }
 }
 
