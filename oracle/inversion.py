@@ -115,3 +115,56 @@ def invert_cg(mesh, obs, d_obs, wdepth, lam, m_ref=None, tol=1e-6, max_iter=200,
         max_iter=max_iter, fixed_iters=fixed_iters)
     m = m_ref + cov * prism.adjoint(mesh, obs, y)
     return m, y, it, hist
+
+
+def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5):
+    """The paper's solver policy (Section 2.2: at most `outer` model updates,
+    each at most `inner` CG iterations, stop at res <= tol, step-size
+    backtracking), in the reading used here:
+
+    * outer cycle: restart CG from the current y with the true residual
+      r = b - A y and p = r; run up to `inner` iterations (stop early when
+      ||r|| / ||b|| <= tol);
+    * backtracking: Q(y) = y^T A y / 2 - y^T b = -(y^T (b + r)) / 2 is the
+      quadratic the data-space system minimises; while the cycle raised Q,
+      halve its step (y <- y_old + (y - y_old) / 2, r recomputed), at most
+      `max_halvings` times;
+    * stop when ||r|| / ||b|| <= tol after a cycle, or after `outer` cycles.
+
+    Returns (y, total_inner_iterations, outer_cycles, relres_history)."""
+    b = np.asarray(b, dtype=np.float64)
+    y = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    hist = [1.0]
+    total = 0
+    q_old = 0.0
+    cycles = 0
+    for cycles in range(1, outer + 1):
+        y_old = y.copy()
+        r = b - apply(y)
+        p = r.copy()
+        rr = float(r @ r)
+        for _ in range(inner):
+            if np.sqrt(rr) / bnorm <= tol:
+                break
+            q = apply(p)
+            alpha = rr / float(p @ q)
+            y = y + alpha * p
+            r = r - alpha * q
+            rr_new = float(r @ r)
+            p = r + (rr_new / rr) * p
+            rr = rr_new
+            total += 1
+        r = b - apply(y)
+        q_new = -0.5 * float(y @ (b + r))
+        halvings = 0
+        while q_new > q_old and halvings < max_halvings:
+            y = y_old + 0.5 * (y - y_old)
+            r = b - apply(y)
+            q_new = -0.5 * float(y @ (b + r))
+            halvings += 1
+        q_old = q_new
+        hist.append(float(np.linalg.norm(r)) / bnorm)
+        if hist[-1] <= tol:
+            break
+    return y, total, cycles, hist

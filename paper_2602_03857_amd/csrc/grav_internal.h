@@ -9,7 +9,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/grav.h"
+#include "grav.h"
 
 namespace grav {
 

@@ -372,3 +372,47 @@ def test_config1_model_geometry():
     assert p.mesh.ncells == 16384 and p.obs.n == 1024
     assert int((p.m > 0).sum()) == 320
     assert np.all(p.obs.z == p.mesh.zn[0])
+
+
+def test_restarted_cg_policy_converges_to_cholesky():
+    """The restarted policy reaches the Cholesky solution of Eq. 11 given
+    enough cycles (short cycles: 4 inner iterations), and the quadratic it
+    minimises, Q(y) = y^T A y / 2 - y^T b, never rises from one cycle to the next."""
+    p, G, cov, d_obs, lam = _tiny_problem(8)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    y_chol = np.linalg.solve(A, d_obs)
+    y, total, cycles, hist = inversion.restarted_cg(lambda v: A @ v, d_obs, inner=4, outer=200,
+                                                    tol=1e-12)
+    assert hist[-1] <= 1e-12 and cycles < 200 and total <= 4 * cycles
+    assert np.linalg.norm(y - y_chol) <= 1e-9 * np.linalg.norm(y_chol)
+    qs = []
+    for k in range(1, 8):
+        yk, _, _, _ = inversion.restarted_cg(lambda v: A @ v, d_obs, inner=2, outer=k, tol=0.0)
+        qs.append(0.5 * yk @ A @ yk - yk @ d_obs)
+    assert np.all(np.diff(qs) <= 1e-12 * abs(qs[0]))
+    # one long cycle is plain CG: 20 inner iterations on N = 10 reach the solution
+    y1, total1, cycles1, _ = inversion.restarted_cg(lambda v: A @ v, d_obs, tol=1e-12)
+    y_cg, it_cg, _ = inversion.conjugate_gradient(lambda v: A @ v, d_obs, tol=1e-12, max_iter=20)
+    assert cycles1 == 1 and total1 == it_cg
+    np.testing.assert_allclose(y1, y_cg, rtol=1e-12, atol=1e-12 * np.abs(y_cg).max())
+
+
+def test_restarted_cg_backtracking_halves_a_rising_step():
+    """Backtracking: with an operator whose cycle overshoots (a large skew part
+    makes CG steps too long for the symmetric quadratic), the unguarded cycle
+    raises Q above Q(0) = 0 and the guarded one halves the step back below it."""
+    rng = np.random.default_rng(0)
+    n = 12
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    S = Q @ np.diag(np.logspace(0, 3, n)) @ Q.T
+    K = rng.standard_normal((n, n))
+    A = S + 50.0 * (K - K.T)
+    b = rng.standard_normal(n)
+    quad = lambda y: 0.5 * y @ S @ y - y @ b  # noqa: E731  (y^T A y = y^T S y)
+    y0, _, _, _ = inversion.restarted_cg(lambda v: A @ v, b, inner=5, outer=1, tol=0.0,
+                                         max_halvings=0)
+    y1, _, _, _ = inversion.restarted_cg(lambda v: A @ v, b, inner=5, outer=1, tol=0.0)
+    assert quad(y0) > 0.0 > quad(y1)
+    # the guarded step is the unguarded one halved k times
+    ratios = y1 / y0
+    assert np.allclose(ratios, ratios[0]) and np.log2(1.0 / ratios[0]) in (1, 2, 3, 4, 5)
