@@ -105,7 +105,7 @@ typedef struct grav_ctx grav_ctx;
 /* Operation codes for grav_workspace_bytes(). */
 typedef enum {
     GRAV_OP_FORWARD = 0, GRAV_OP_ADJOINT = 1, GRAV_OP_DATASPACE = 2, GRAV_OP_TRACE = 3,
-    GRAV_OP_INVERT = 4, GRAV_OP_FORWARD_MULTI = 5
+    GRAV_OP_INVERT = 4, GRAV_OP_FORWARD_MULTI = 5, GRAV_OP_TREND = 6
 } grav_op;
 
 /* Fill `opts` with the defaults (device 0, validate 1, 4 GiB workspace). */
@@ -126,8 +126,9 @@ void grav_ctx_destroy(grav_ctx *ctx);
 const char *grav_last_error(const grav_ctx *ctx);
 
 /* Device workspace bytes that `op` needs for this shape and precision (K =
- * models for GRAV_OP_FORWARD_MULTI, ignored otherwise).  Host-only; 0 means
- * the shape or combination is invalid. */
+ * models for GRAV_OP_FORWARD_MULTI, ignored otherwise; GRAV_OP_TREND ignores
+ * nx, ny, nz, n and prec).  Host-only; 0 means the shape or combination is
+ * invalid. */
 uint64_t grav_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int64_t n, grav_op op,
                               grav_prec prec, int32_t K);
 
@@ -168,13 +169,37 @@ typedef struct {
                             M = diag(G C G^T) + lambda I (the trace sweep's
                             per-observation terms; grav_invert only, the
                             server requires 0) */
+    /* Restarted CG, the solver policy of Section 2.2 (bounded inner CG runs
+     * inside bounded outer model updates, with step backtracking).  With
+     * restart > 0: each cycle restarts CG from the current y with the true
+     * residual r = delta_d - A y and p = r and runs at most `restart`
+     * iterations (leaving early once the recursive residual meets tol); after
+     * the cycle the true residual is formed and, while the cycle raised
+     * Q(y) = y^T A y / 2 - y^T delta_d, its step is halved (at most
+     * `max_halvings` times); the solve stops when the true relative residual
+     * meets tol or after `max_cycles` cycles.  max_iter and fixed_iters are
+     * then unused (fixed_iters must be 0) and precond must be 0.
+     * grav_invert only: the server requires restart = 0. */
+    int32_t restart;      /* 0: plain (or Jacobi) CG as above; > 0: inner iteration cap */
+    int32_t max_cycles;   /* restarted CG: outer cycle cap (>= 1) */
+    int32_t max_halvings; /* restarted CG: step halvings per cycle (>= 0; 0 = no backtracking) */
+    /* Misfit log: if history is non-NULL (HOST array of history_cap doubles),
+     * entry k receives ||r_k|| / ||delta_d|| (the recursive residual) after
+     * CG iteration k+1, over all cycles in order, for the first history_cap
+     * iterations; later entries are untouched.  Not written with
+     * fixed_iters > 0 (that mode reads no residual until the end).
+     * grav_invert only: the server requires history_cap = 0. */
+    int32_t history_cap;
+    double *history;
 } grav_cg_opts;
 
 typedef struct {
     int32_t iters;       /* iterations performed */
     double relres;       /* final ||r|| / ||delta_d|| */
     double lambda_used;  /* lambda actually used */
-    double trace;        /* trace(G C G^T) if it was computed (lambda < 0), else 0 */
+    double trace;        /* trace(G C G^T) if it was computed (lambda < 0 or precond), else 0 */
+    int32_t cycles;      /* restarted CG: outer cycles run (else 1) */
+    int32_t halvings;    /* restarted CG: step halvings applied in total (else 0) */
 } grav_cg_info;
 
 /* Data-space inversion (paper Eq. 10-11): delta_d = d_obs - G m_ref;
@@ -183,11 +208,34 @@ typedef struct {
  *   lambda = 1e-2 * trace(G C G^T) / n; m_ref : M doubles or NULL (= 0);
  *   m_out : M doubles (output); d_pred : n doubles (output G m_out) or NULL;
  *   info : HOST pointer or NULL.  The call waits for completion.
- * Returns GRAV_OK, GRAV_ENOCONV (max_iter reached, outputs valid), or an error. */
+ * With cg->restart > 0 the solve follows the restarted policy described at
+ * grav_cg_opts; info->iters then counts inner iterations over all cycles.
+ * Returns GRAV_OK, GRAV_ENOCONV (iteration or cycle cap reached, outputs
+ * valid), or an error. */
 int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const double *d_obs,
                 const double *wdepth, double lambda, const double *m_ref,
                 const grav_cg_opts *cg, double *m_out, double *d_pred, grav_cg_info *info,
                 grav_prec prec, grav_stream stream);
+
+/* Regional-residual separation (the second-degree trend-surface removal of
+ * the field workflow, Section 3.2; one surface over the whole domain also
+ * joins sections inverted separately, Section 4.4): least-squares fit
+ *   T(x, y) = sum_j coef[j] phi_j(u, w),  u = (x - x0) / L,  w = (y - y0) / L,
+ *   phi = (1, u, w, u^2, u w, w^2) for degree 2, (1, u, w) for degree 1,
+ * (x0, y0) the centre of the points' bounding box and L half its larger side
+ * (1 for a single point).
+ *   x, y, v : n doubles (DEVICE): station coordinates and values;
+ *   coef : HOST, 6 doubles (output; entries past the degree's basis are 0);
+ *   frame : HOST, 3 doubles (output) {x0, y0, L};
+ *   resid : DEVICE, n doubles (output v - T) or NULL; may alias v;
+ *   trend : DEVICE, n doubles (output T) or NULL.
+ * The call waits for completion.  Errors: GRAV_EINVAL (NULL argument,
+ * degree not 1 or 2, n below the basis size, a non-finite input, points that
+ * do not determine the surface), GRAV_ENOMEM (workspace under
+ * grav_workspace_bytes(.., GRAV_OP_TREND, ..)), GRAV_EDEVICE. */
+int grav_trend_surface(grav_ctx *ctx, const double *x, const double *y, const double *v,
+                       int64_t n, int32_t degree, double *coef, double *frame, double *resid,
+                       double *trend, grav_stream stream);
 
 /* Multi-model forward D = G [m_1 ... m_K] (Eq. 6 for a block of models, a
  * dense contraction over prisms).

@@ -117,7 +117,7 @@ def invert_cg(mesh, obs, d_obs, wdepth, lam, m_ref=None, tol=1e-6, max_iter=200,
     return m, y, it, hist
 
 
-def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5):
+def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5, log=None):
     """The paper's solver policy (Section 2.2: at most `outer` model updates,
     each at most `inner` CG iterations, stop at res <= tol, step-size
     backtracking), in the reading used here:
@@ -131,7 +131,11 @@ def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5):
       `max_halvings` times;
     * stop when ||r|| / ||b|| <= tol after a cycle, or after `outer` cycles.
 
-    Returns (y, total_inner_iterations, outer_cycles, relres_history)."""
+    If ``log`` is a list, the recursive relative residual after every inner
+    iteration is appended to it (the misfit-versus-iteration record).
+
+    Returns (y, total_inner_iterations, outer_cycles, relres_history), the
+    history holding the true relative residual after each cycle."""
     b = np.asarray(b, dtype=np.float64)
     y = np.zeros_like(b)
     bnorm = np.linalg.norm(b)
@@ -155,6 +159,8 @@ def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5):
             p = r + (rr_new / rr) * p
             rr = rr_new
             total += 1
+            if log is not None:
+                log.append(np.sqrt(rr) / bnorm)
         r = b - apply(y)
         q_new = -0.5 * float(y @ (b + r))
         halvings = 0

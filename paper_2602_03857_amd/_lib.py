@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrav.so"
 
 GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV, GRAV_EBUSY = range(6)
 GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU = range(4)
-OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI = range(6)
+OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND = range(7)
 GRAV_GAMMA = 6.674e-11
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -31,12 +31,16 @@ class CtxOpts(ctypes.Structure):
 
 class CgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("fixed_iters", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("fixed_iters", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("history_cap", ctypes.c_int32),
+                ("history", ctypes.POINTER(ctypes.c_double))]
 
 
 class CgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double),
-                ("lambda_used", ctypes.c_double), ("trace", ctypes.c_double)]
+                ("lambda_used", ctypes.c_double), ("trace", ctypes.c_double),
+                ("cycles", ctypes.c_int32), ("halvings", ctypes.c_int32)]
 
 
 class GravRequest(ctypes.Structure):
@@ -86,6 +90,8 @@ def _load():
         "grav_dataspace_apply": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, dbl, vp, vp,
                                                 ctypes.c_int, vp]),
         "grav_trace": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, P(dbl), vp, ctypes.c_int, vp]),
+        "grav_trend_surface": (ctypes.c_int, [vp, vp, vp, vp, i64, i32, P(dbl), P(dbl), vp, vp,
+                                              vp]),
         "grav_invert": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, vp, dbl, vp, P(CgOpts), vp, vp,
                                        P(CgInfo), ctypes.c_int, vp]),
         "grav_forward_multi": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, i32, vp, ctypes.c_int,
@@ -111,6 +117,7 @@ lib = _load()
 EXPORTED = [
     "grav_ctx_opts_default", "grav_ctx_create", "grav_ctx_destroy", "grav_last_error",
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
+    "grav_trend_surface",
     "grav_invert", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
     "grav_reset_timing", "grav_server_create", "grav_server_submit", "grav_server_poll",
     "grav_server_wait", "grav_server_destroy",

@@ -189,10 +189,36 @@ class Context:
                                 self._stream(stream)))
         return tr.value
 
+    def trend_surface(self, x, y, v, degree=2, resid=None, trend=None, stream=None):
+        """Least-squares trend surface of `degree` (1 or 2) through (x, y, v)
+        (device float64 vectors of one length).  Returns (coef[6], frame
+        (x0, y0, L)) and fills `resid` (v - T) and/or `trend` (T) if given."""
+        n = v.numel()
+        for t, name in ((x, "x"), (y, "y"), (v, "v")):
+            _check(t, torch.float64, n, name, self.device)
+        for t, name in ((resid, "resid"), (trend, "trend")):
+            if t is not None:
+                _check(t, torch.float64, n, name, self.device)
+        coef = (ctypes.c_double * 6)()
+        frame = (ctypes.c_double * 3)()
+        self._rc(lib.grav_trend_surface(self._h, x.data_ptr(), y.data_ptr(), v.data_ptr(), n,
+                                        int(degree), coef, frame,
+                                        resid.data_ptr() if resid is not None else None,
+                                        trend.data_ptr() if trend is not None else None,
+                                        self._stream(stream)))
+        return list(coef), tuple(frame)
+
     def invert(self, mesh, obs, d_obs, wdepth, lam=-1.0, m_ref=None, tol=1e-6, max_iter=200,
                fixed_iters=0, m_out=None, d_pred=None, want_pred=False, prec=GRAV_MIXED,
-               stream=None, precond=0):
-        """Data-space CG inversion (Eq. 11).  Returns (m, d_pred or None, info dict)."""
+               stream=None, precond=0, restart=0, max_cycles=30, max_halvings=5,
+               history_cap=0):
+        """Data-space CG inversion (Eq. 11).  Returns (m, d_pred or None, info dict).
+
+        restart > 0 selects the restarted policy (cycles of at most `restart`
+        CG iterations, at most `max_cycles` cycles, step backtracking with at
+        most `max_halvings` halvings per cycle); max_iter is then unused.
+        history_cap > 0 returns the misfit log (relative residual after each
+        CG iteration, at most history_cap entries) as info["history"]."""
         _check(d_obs, torch.float64, obs.n, "d_obs", self.device)
         _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
         if m_ref is not None:
@@ -204,7 +230,10 @@ class Context:
             d_pred = torch.empty(obs.n, dtype=torch.float64, device=self.device)
         if d_pred is not None:
             _check(d_pred, torch.float64, obs.n, "d_pred", self.device)
-        cg = CgOpts(float(tol), int(max_iter), int(fixed_iters), int(precond))
+        hist = (ctypes.c_double * max(int(history_cap), 1))()
+        cg = CgOpts(float(tol), int(max_iter), int(fixed_iters), int(precond), int(restart),
+                    int(max_cycles), int(max_halvings), int(history_cap),
+                    ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history_cap > 0 else None)
         info = CgInfo()
         rc = lib.grav_invert(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c), d_obs.data_ptr(),
                              wdepth.data_ptr(), float(lam),
@@ -214,6 +243,9 @@ class Context:
         self._rc(rc, allow_noconv=True)
         return m_out, d_pred, dict(iters=info.iters, relres=info.relres,
                                    lambda_used=info.lambda_used, trace=info.trace,
+                                   cycles=info.cycles, halvings=info.halvings,
+                                   history=(list(hist[:min(info.iters, history_cap)])
+                                            if history_cap > 0 and not fixed_iters else None),
                                    converged=(rc == GRAV_OK))
 
     def forward_multi(self, mesh, obs, models, D=None, prec=GRAV_MIXED_BF16X3, stream=None):

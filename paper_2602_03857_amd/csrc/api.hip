@@ -272,6 +272,7 @@ extern "C" const char *grav_last_error(const grav_ctx *ctx) {
 
 extern "C" uint64_t grav_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int64_t n, grav_op op,
                                          grav_prec prec, int32_t K) {
+    if (op == GRAV_OP_TREND) return grav::trend_workspace_need();
     if (nx <= 0 || ny <= 0 || nz <= 0 || n <= 0) return 0;
     return grav::workspace_need(nx, ny, nz, n, op, prec, K);
 }
@@ -358,6 +359,17 @@ extern "C" int grav_trace(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *
     return op_trace(ctx, ar, g, o, wdepth, trace, diag, prec, st);
 }
 
+extern "C" int grav_trend_surface(grav_ctx *ctx, const double *x, const double *y, const double *v,
+                                  int64_t n, int32_t degree, double *coef, double *frame,
+                                  double *resid, double *trend, grav_stream stream) {
+    ENTER(ctx);
+    if (!x || !y || !v || !coef || !frame) return fail(ctx, GRAV_EINVAL, "x, y, v, coef or frame is NULL");
+    if (degree != 1 && degree != 2) return fail(ctx, GRAV_EINVAL, "degree must be 1 or 2");
+    if (n < (degree == 2 ? 6 : 3)) return fail(ctx, GRAV_EINVAL, "fewer points than basis functions");
+    return grav::op_trend_surface(ctx, x, y, v, n, degree, coef, frame, resid, trend,
+                                  reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
                            const double *d_obs, const double *wdepth, double lambda,
                            const double *m_ref, const grav_cg_opts *cg, double *m_out,
@@ -368,8 +380,17 @@ extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs 
     if (rc) return rc;
     if (!d_obs || !wdepth || !cg || !m_out) return fail(ctx, GRAV_EINVAL, "d_obs, wdepth, cg or m_out is NULL");
     if (!std::isfinite(lambda)) return fail(ctx, GRAV_EINVAL, "lambda must be finite");
-    if (cg->fixed_iters <= 0 && (cg->max_iter < 1 || !(cg->tol >= 0.0)))
+    if (cg->restart < 0) return fail(ctx, GRAV_EINVAL, "restart must be >= 0");
+    if (cg->history_cap < 0 || (cg->history_cap > 0 && !cg->history))
+        return fail(ctx, GRAV_EINVAL, "history_cap must be >= 0, with a history array when > 0");
+    if (cg->restart > 0) {
+        if (cg->max_cycles < 1 || cg->max_halvings < 0 || !(cg->tol >= 0.0))
+            return fail(ctx, GRAV_EINVAL, "restarted CG needs max_cycles >= 1, max_halvings >= 0, tol >= 0");
+        if (cg->fixed_iters != 0 || cg->precond != 0)
+            return fail(ctx, GRAV_EINVAL, "restarted CG needs fixed_iters = 0 and precond = 0");
+    } else if (cg->fixed_iters <= 0 && (cg->max_iter < 1 || !(cg->tol >= 0.0))) {
         return fail(ctx, GRAV_EINVAL, "CG needs max_iter >= 1 and tol >= 0, or fixed_iters > 0");
+    }
     if (cg->precond != 0 && cg->precond != 1)
         return fail(ctx, GRAV_EINVAL, "precond must be 0 (none) or 1 (Jacobi)");
     if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");

@@ -57,6 +57,10 @@ int op_adjoint(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const doub
                const double *base);
 int op_dataspace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
                  double lambda, const double *v, double *out, grav_prec prec, hipStream_t st);
+int op_trend_surface(grav_ctx *ctx, const double *x, const double *y, const double *v, int64_t n,
+                     int degree, double *coef, double *frame, double *resid, double *trend,
+                     hipStream_t st);
+uint64_t trend_workspace_need();
 int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
              double *trace, double *diag, grav_prec prec, hipStream_t st);
 int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,

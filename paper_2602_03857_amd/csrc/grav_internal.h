@@ -123,7 +123,11 @@ hipError_t launch_validate_finite(const double *w, int64_t len, int *flags, hipS
 
 // ---- vector kernels for CG ------------------------------------------------
 constexpr int kDotBlocks = 512;
-enum : int { kRR = 0, kPQ = 1, kRRNew = 2, kB2 = 3, kAlpha = 4, kBeta = 5, kRZ = 6, kNumScalars = 8 };
+enum : int {
+    kRR = 0, kPQ = 1, kRRNew = 2, kB2 = 3, kAlpha = 4, kBeta = 5, kRZ = 6,
+    kYB = 7,                // restarted CG: y . (delta_d + r), i.e. -2 Q(y)
+    kNumScalars = 8
+};
 enum : int {
     kFinishInit = 0, kFinishPQ = 1, kFinishRRNew = 2, kFinishPlain = 3,
     kFinishPQPrecond = 4,   // alpha = (r.z) / (p.Ap)
@@ -149,5 +153,8 @@ hipError_t launch_cg_update_p(double *p, const double *r, int64_t n, const doubl
 // dst = a - b (b may be null: dst = a)
 hipError_t launch_sub(const double *a, const double *b, double *dst, int64_t n, hipStream_t st);
 hipError_t launch_fill(double *dst, double value, int64_t n, hipStream_t st);
+// dst = ca a + cb b (dst may alias a or b)
+hipError_t launch_lincomb(double *dst, double ca, const double *a, double cb, const double *b,
+                          int64_t n, hipStream_t st);
 
 }  // namespace grav

@@ -23,6 +23,86 @@ static int read_scalars(grav_ctx *ctx, hipStream_t st) {
     return GRAV_OK;
 }
 
+// Restarted CG (the solver policy of Section 2.2).  On entry y = 0, r holds
+// delta_d (= dd) and scal[kRR], scal[kB2] hold its squared norm.  Each cycle
+// restarts from the true residual; after a cycle the true residual r = dd - A y
+// is formed and, while Q(y) = -(y . (dd + r)) / 2 rose above the previous
+// cycle's value, the step is halved.  The residual is affine in y, so the
+// halved iterate's residual is the mean of the two residuals and needs no
+// operator application.
+struct SolveStats {
+    int iters = 0, cycles = 0, halvings = 0;
+    double relres = 0.0;
+    bool converged = false;
+};
+
+static int restarted_cg(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
+                        double lambda, grav_prec prec, hipStream_t st, const grav_cg_opts &cg,
+                        const double *dd, double *y, double *r, double *p, double *q, double *yold,
+                        double *rold, double b2, SolveStats *out) {
+    const int64_t n = o.n;
+    double *scal = ctx_scalars(ctx);
+    double *dpart = ctx_dot_partials(ctx);
+    double *dpart2 = ctx_dot_partials2(ctx);
+    SolveStats s;
+    s.relres = b2 > 0.0 ? 1.0 : 0.0;
+    s.converged = b2 == 0.0;
+    double rr = b2;         // r . r of the current (true) residual
+    double q_prev = 0.0;    // Q(0) = 0
+    // Q(y) and r.r of the current y, r
+    auto objective = [&](double *q_val) -> int {
+        HIP_TRY(launch_lincomb(q, 1.0, dd, 1.0, r, n, st), "lincomb");
+        HIP_TRY(launch_dot(y, q, n, dpart, st), "dot");
+        HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kYB, st), "dot");
+        HIP_TRY(launch_dot(r, r, n, dpart2, st), "dot");
+        HIP_TRY(launch_dot_finish(dpart2, scal, kFinishPlain, kRR, st), "dot");
+        int rc = read_scalars(ctx, st);
+        if (rc) return rc;
+        *q_val = -0.5 * ctx->h_scal[kYB];
+        rr = ctx->h_scal[kRR];
+        return GRAV_OK;
+    };
+    while (s.cycles < cg.max_cycles && !s.converged) {
+        ++s.cycles;
+        HIP_TRY(launch_sub(y, nullptr, yold, n, st), "copy");
+        HIP_TRY(launch_sub(r, nullptr, rold, n, st), "copy");
+        HIP_TRY(launch_sub(r, nullptr, p, n, st), "copy");
+        for (int j = 0; j < cg.restart && std::sqrt(rr / b2) > cg.tol; ++j) {
+            int rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
+            if (rc) return rc;
+            HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQ, 0, st), "dot");
+            HIP_TRY(launch_cg_update_yr(y, r, p, q, n, scal, dpart, st), "cg update");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishRRNew, 0, st), "dot");
+            rc = read_scalars(ctx, st);
+            if (rc) return rc;
+            rr = ctx->h_scal[kRR];
+            if (s.iters < cg.history_cap && cg.history) cg.history[s.iters] = std::sqrt(rr / b2);
+            ++s.iters;
+            HIP_TRY(launch_cg_update_p(p, r, n, scal, st), "cg update");
+        }
+        // true residual r = dd - A y
+        int rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, y, q, prec, st);
+        if (rc) return rc;
+        HIP_TRY(launch_sub(dd, q, r, n, st), "residual");
+        double q_new = 0.0;
+        rc = objective(&q_new);
+        if (rc) return rc;
+        for (int h = 0; h < cg.max_halvings && q_new > q_prev; ++h) {
+            HIP_TRY(launch_lincomb(y, 0.5, y, 0.5, yold, n, st), "halve");
+            HIP_TRY(launch_lincomb(r, 0.5, r, 0.5, rold, n, st), "halve");
+            rc = objective(&q_new);
+            if (rc) return rc;
+            ++s.halvings;
+        }
+        q_prev = q_new;
+        s.relres = std::sqrt(rr / b2);
+        s.converged = s.relres <= cg.tol;
+    }
+    *out = s;
+    return GRAV_OK;
+}
+
 int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
                const double *wdepth, double lambda, const double *m_ref, const grav_cg_opts &cg,
                double *m_out, double *d_pred, grav_cg_info *info, grav_prec prec, hipStream_t st) {
@@ -35,6 +115,10 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
     const bool pc = cg.precond == 1;            // Jacobi preconditioner
     double *z = pc ? ar.take<double>(n) : nullptr;
     double *dinv = pc ? ar.take<double>(n) : nullptr;
+    const bool restarted = cg.restart > 0;      // delta_d, y and r of the cycle start
+    double *dd = restarted ? ar.take<double>(n) : nullptr;
+    double *yold = restarted ? ar.take<double>(n) : nullptr;
+    double *rold = restarted ? ar.take<double>(n) : nullptr;
     if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the CG vectors");
     double *scal = ctx_scalars(ctx);
     double *dpart = ctx_dot_partials(ctx);
@@ -68,12 +152,24 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
     if (rc) return rc;
     const double b2 = ctx->h_scal[kB2];
 
-    const bool fixed = cg.fixed_iters > 0;
-    const int iters_cap = fixed ? cg.fixed_iters : cg.max_iter;
-    int it = 0;
+    const bool fixed = !restarted && cg.fixed_iters > 0;
+    const int iters_cap = restarted ? 0 : fixed ? cg.fixed_iters : cg.max_iter;
+    int it = 0, cycles = 1, halvings = 0;
     double relres = b2 > 0.0 ? 1.0 : 0.0;
     bool converged = b2 == 0.0;
-    for (it = 0; it < iters_cap && !converged;) {
+    if (restarted) {
+        HIP_TRY(launch_sub(r, nullptr, dd, n, st), "copy");
+        SolveStats ss;
+        rc = restarted_cg(ctx, ar, g, o, wdepth, lambda, prec, st, cg, dd, y, r, p, q, yold, rold,
+                          b2, &ss);
+        if (rc) return rc;
+        it = ss.iters;
+        cycles = ss.cycles;
+        halvings = ss.halvings;
+        relres = ss.relres;
+        converged = ss.converged;
+    }
+    for (it = restarted ? it : 0; it < iters_cap && !converged;) {
         rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
         if (rc) return rc;
         HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
@@ -92,6 +188,7 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
             rc = read_scalars(ctx, st);
             if (rc) return rc;
             relres = std::sqrt(ctx->h_scal[kRR] / b2);
+            if (it - 1 < cg.history_cap && cg.history) cg.history[it - 1] = relres;
             if (relres <= cg.tol) { converged = true; break; }
         }
         HIP_TRY(launch_cg_update_p(p, pc ? z : r, n, scal, st), "cg update");
@@ -115,9 +212,12 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
         info->relres = relres;
         info->lambda_used = lambda;
         info->trace = trace;
+        info->cycles = cycles;
+        info->halvings = halvings;
     }
     if (!fixed && !converged) {
-        ctx->err = "CG reached max_iter before tol";
+        ctx->err = restarted ? "restarted CG reached max_cycles before tol"
+                             : "CG reached max_iter before tol";
         return GRAV_ENOCONV;
     }
     return GRAV_OK;
@@ -182,7 +282,7 @@ uint64_t workspace_need(int nx, int ny, int nz, int64_t n, grav_op op, grav_prec
             return need_trace(g, n);
         case GRAV_OP_INVERT: {
             Counter c;
-            for (int i = 0; i < 6; ++i) c.take<double>(n);
+            for (int i = 0; i < 7; ++i) c.take<double>(n);   // CG vectors (restarted: 7)
             size_t inner = need_dataspace(g, n, prec);
             const size_t t = need_trace(g, n);
             if (t > inner) inner = t;

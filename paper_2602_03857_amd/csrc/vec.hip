@@ -157,6 +157,14 @@ __global__ void k_sub(const double *__restrict__ a, const double *__restrict__ b
         dst[i] = b ? a[i] - b[i] : a[i];
 }
 
+// dst = ca a + cb b; dst may alias a or b (element-wise).
+__global__ void k_lincomb(double *dst, double ca, const double *a, double cb, const double *b,
+                          int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = fma(ca, a[i], cb * b[i]);
+}
+
 __global__ void k_fill(double *__restrict__ dst, double value, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -212,6 +220,12 @@ hipError_t launch_cg_update_p(double *p, const double *r, int64_t n, const doubl
 
 hipError_t launch_sub(const double *a, const double *b, double *dst, int64_t n, hipStream_t st) {
     k_sub<<<grid_vec(n), 256, 0, st>>>(a, b, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double *dst, double ca, const double *a, double cb, const double *b,
+                          int64_t n, hipStream_t st) {
+    k_lincomb<<<grid_vec(n), 256, 0, st>>>(dst, ca, a, cb, b, n);
     return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@ import os
 import numpy as np
 import pytest
 
+from oracle import trend as trend_oracle
 from oracle import prism, inversion, GAMMA
 import workloads
 from tests._util import load_package, rel_l2, to_np
@@ -266,6 +267,19 @@ def test_invert_jacobi_preconditioned(g, ctx, config1_ref, prec_name):
     assert err <= 1e-4
 
 
+def test_invert_misfit_history_plain_cg(g, ctx, config1_ref):
+    """Misfit log of plain CG against the oracle's residual history."""
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    cov = inversion.covariance_from_weights(p.wdepth)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    _, it_ref, hist = inversion.conjugate_gradient(lambda v: A @ v, d_obs, tol=1e-6, max_iter=500)
+    _, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-6, max_iter=500,
+                            prec=g.GRAV_FP64, history_cap=30)
+    assert info["iters"] == it_ref > 30 and len(info["history"]) == 30
+    np.testing.assert_allclose(info["history"], hist[1:31], rtol=1e-6)
+
+
 def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
     p, G, d_obs, trace, lam, m_chol = config1_ref
     mesh, obs = _dev(g, p)
@@ -280,6 +294,58 @@ def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
     m2, _, info2 = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-12, max_iter=3)
     assert not info2["converged"] and info2["iters"] == 3
     assert np.all(np.isfinite(to_np(m2)))
+
+
+@pytest.mark.parametrize("prec_name,tol", [("GRAV_FP64", 1e-4), ("GRAV_FP64", 1e-6),
+                                           ("GRAV_MIXED", 1e-4)])
+def test_invert_restarted_policy(g, ctx, config1_ref, prec_name, tol):
+    """Restarted CG (Section 2.2 policy: at most 20 inner iterations in at most
+    30 cycles, step backtracking) against the oracle's restarted CG on the
+    dense system of Eq. 11: same cycles, same inner iterations (FP64) and the
+    same iterate."""
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    cov = inversion.covariance_from_weights(p.wdepth)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    log = []
+    y_ref, iters_ref, cycles_ref, hist = inversion.restarted_cg(lambda v: A @ v, d_obs, 20, 30, tol,
+                                                                log=log)
+    m_ref = cov * (G.T @ y_ref)
+    m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=tol, restart=20,
+                            max_cycles=30, max_halvings=5, prec=getattr(g, prec_name),
+                            history_cap=1000)
+    print(f"[parity] restarted CG {prec_name} tol {tol}: {info} (oracle {iters_ref} iterations, "
+          f"{cycles_ref} cycles)", flush=True)
+    assert info["converged"] and info["relres"] <= tol
+    assert info["cycles"] == cycles_ref
+    exact = prec_name == "GRAV_FP64"
+    assert abs(info["iters"] - iters_ref) <= (0 if exact else 2)
+    assert abs(info["relres"] - hist[-1]) <= (1e-6 if exact else 0.5) * hist[-1]
+    # misfit log: one entry per inner iteration, the oracle's recursive residuals
+    assert len(info["history"]) == info["iters"]
+    if exact:
+        np.testing.assert_allclose(info["history"], log, rtol=1e-6)
+    err = rel_l2(to_np(m), m_ref)
+    _report(f"restarted CG config1 {prec_name} tol {tol} vs oracle", err)
+    assert err <= (1e-6 if exact else 1e-3)
+    assert rel_l2(to_np(m), m_chol) <= 10 * tol
+
+
+def test_invert_restarted_cycle_cap_and_errors(g, ctx, config1_ref):
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    cov = inversion.covariance_from_weights(p.wdepth)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    y_ref, _, _, hist = inversion.restarted_cg(lambda v: A @ v, d_obs, 5, 3, 1e-12)
+    m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-12, restart=5,
+                            max_cycles=3, prec=g.GRAV_FP64)
+    assert not info["converged"] and info["cycles"] == 3 and info["iters"] == 15
+    assert rel_l2(to_np(m), cov * (G.T @ y_ref)) <= 1e-8
+    assert abs(info["relres"] - hist[-1]) <= 1e-6 * hist[-1]
+    for bad in (dict(restart=5, max_cycles=0), dict(restart=5, precond=1),
+                dict(restart=5, fixed_iters=3), dict(restart=-1), dict(restart=5, max_halvings=-1)):
+        with pytest.raises(g.GravError):
+            ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-4, **bad)
 
 
 def test_invert_with_reference_model(g, ctx):
@@ -444,3 +510,62 @@ def test_error_paths(g, ctx):
     with pytest.raises(g.GravError):
         ctx.forward(mesh, obs, m, prec=g.GRAV_MIXED_BF16X3)
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ trend surface
+
+def _regional_field(seed, n):
+    """Stations over a 128 km x 220 km block (the extent of the regional
+    survey) with a second-degree regional trend plus local anomalies and noise."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.28e5, n) + 3.0e5
+    y = rng.uniform(0.0, 2.2e5, n) + 2.6e6
+    u, w = (x - 3.64e5) / 1e5, (y - 2.71e6) / 1e5
+    regional = 4e-4 - 2e-4 * u + 1e-4 * w + 5e-5 * u * u - 8e-5 * u * w + 3e-5 * w * w
+    local = sum(a * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * s * s))
+                for a, cx, cy, s in zip(rng.normal(0, 2e-5, 12), rng.uniform(3e5, 4.28e5, 12),
+                                        rng.uniform(2.6e6, 2.82e6, 12), rng.uniform(2e3, 1.5e4, 12)))
+    return x, y, regional + local + 1e-6 * rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("n,degree", [(7, 2), (1000, 1), (178797, 2)])
+def test_trend_surface_vs_oracle(g, ctx, n, degree):
+    import torch
+    x, y, v = _regional_field(50 + n, n)
+    t_ref, r_ref = trend_oracle.trend_surface(x, y, v, degree)
+    tx, ty, tv = _t(x), _t(y), _t(v)
+    resid = torch.empty_like(tv)
+    tr = torch.empty_like(tv)
+    coef, frame = ctx.trend_surface(tx, ty, tv, degree, resid=resid, trend=tr)
+    print(f"[parity] trend n={n} degree={degree}: frame {frame}", flush=True)
+    scale = np.abs(t_ref).max()
+    np.testing.assert_allclose(to_np(tr), t_ref, rtol=0, atol=1e-9 * scale)
+    np.testing.assert_allclose(to_np(resid), r_ref, rtol=0, atol=1e-9 * scale)
+    # the returned coefficients and frame describe the same surface
+    u, w = (x - frame[0]) / frame[2], (y - frame[1]) / frame[2]
+    host = np.stack([np.ones_like(u), u, w, u * u, u * w, w * w], 1) @ np.asarray(coef)
+    np.testing.assert_allclose(host, t_ref, rtol=0, atol=1e-9 * scale)
+    if degree == 1:
+        assert coef[3:] == [0.0, 0.0, 0.0]
+    # residual in place, bitwise equal to the separate output
+    tv2 = tv.clone()
+    ctx.trend_surface(tx, ty, tv2, degree, resid=tv2)
+    assert torch.equal(tv2, resid)
+
+
+def test_trend_surface_errors(g, ctx):
+    import torch
+    x, y, v = _regional_field(9, 40)
+    tx, ty, tv = _t(x), _t(y), _t(v)
+    with pytest.raises(g.GravError):
+        ctx.trend_surface(tx, ty, tv, 3)
+    with pytest.raises(g.GravError):
+        ctx.trend_surface(tx[:5], ty[:5], tv[:5], 2)
+    with pytest.raises(g.GravError):      # collinear stations do not fix a quadratic
+        ctx.trend_surface(torch.full_like(tx, 3e5), ty, tv, 2)
+    bad = tv.clone()
+    bad[17] = float("nan")
+    with pytest.raises(g.GravError):
+        ctx.trend_surface(tx, ty, bad, 2)
+    coef, frame = ctx.trend_surface(tx, ty, tv, 2)     # the context still works
+    assert np.all(np.isfinite(coef))

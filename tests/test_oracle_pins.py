@@ -11,7 +11,7 @@ import mpmath as mp
 import numpy as np
 import pytest
 
-from oracle import GAMMA, prism, inversion
+from oracle import GAMMA, prism, inversion, trend
 from workloads import Mesh, Survey, random_case, regular_mesh, config1
 
 
@@ -416,3 +416,47 @@ def test_restarted_cg_backtracking_halves_a_rising_step():
     # the guarded step is the unguarded one halved k times
     ratios = y1 / y0
     assert np.allclose(ratios, ratios[0]) and np.log2(1.0 / ratios[0]) in (1, 2, 3, 4, 5)
+
+
+# ------------------------------------------------------------------ trend surface
+
+def _stations(seed, n):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(2.0e5, 3.3e5, n), rng.uniform(2.6e6, 2.82e6, n), rng
+
+
+def test_trend_surface_recovers_planted_quadratic():
+    """A field that is exactly a second-degree polynomial is its own trend:
+    residual zero to rounding; a first-degree fit of a plane likewise."""
+    x, y, rng = _stations(1, 500)
+    u, w = (x - 2.6e5) / 1e5, (y - 2.7e6) / 1e5
+    quad = 3.0 - 1.5 * u + 0.7 * w + 0.25 * u * u - 0.4 * u * w + 0.9 * w * w
+    t, r = trend.trend_surface(x, y, quad, 2)
+    assert np.abs(r).max() <= 1e-10 * np.abs(quad).max()
+    plane = 3.0 - 1.5 * u + 0.7 * w
+    t1, r1 = trend.trend_surface(x, y, plane, 1)
+    assert np.abs(r1).max() <= 1e-10 * np.abs(plane).max()
+
+
+def test_trend_surface_residual_is_orthogonal_to_the_basis():
+    """Normal equations: the residual is orthogonal to every monomial of the
+    degree, and adding any such polynomial to the data leaves it unchanged."""
+    x, y, rng = _stations(2, 700)
+    v = rng.standard_normal(700) + np.sin(x / 2e4)
+    _, r = trend.trend_surface(x, y, v, 2)
+    xs, ys = (x - x.min()) / 1e5, (y - y.min()) / 1e5
+    for col in (np.ones_like(xs), xs, ys, xs * xs, xs * ys, ys * ys):
+        assert abs(col @ r) <= 1e-10 * np.linalg.norm(col) * np.linalg.norm(v)
+    _, r2 = trend.trend_surface(x, y, v + 5.0 + 2.0 * xs - 3.0 * xs * ys, 2)
+    np.testing.assert_allclose(r2, r, atol=1e-10 * np.abs(v).max())
+
+
+def test_trend_surface_plane_on_symmetric_grid_closed_form():
+    """On a grid symmetric about its centre the monomials 1, u, w are
+    orthogonal, so the first-degree fit is mean(v) + u S_uv / S_uu + w S_wv / S_ww."""
+    u, w = np.meshgrid(np.linspace(-3, 3, 13), np.linspace(-2, 2, 9), indexing="ij")
+    u, w = u.ravel(), w.ravel()
+    v = np.random.default_rng(4).standard_normal(u.size) + np.cos(u * w)
+    t, _ = trend.trend_surface(1e3 * u + 4e5, 1e3 * w + 7e6, v, 1)
+    closed = v.mean() + u * (u @ v) / (u @ u) + w * (w @ v) / (w @ w)
+    np.testing.assert_allclose(t, closed, atol=1e-12 * np.abs(v).max())
