@@ -99,7 +99,7 @@ int op_forward(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const doub
     const size_t mark = ar.off;
     double *part = ar.take<double>((size_t)fp.nchunk * o.n);
     if (prec == GRAV_MIXED) {
-        float *hk = ar.take<float>(g.nz + 1);
+        float *hk = ar.take<float>(layer_table_len(g.nz));
         double *w2 = ar.take<double>(g.nsegs());
         if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the forward sweep");
         HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");
@@ -125,7 +125,7 @@ int op_adjoint(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const doub
     const size_t mark = ar.off;
     if (prec == GRAV_MIXED) {
         const AdjointPlan ap = plan_adjoint(g.ncols(), g.nz, o.n);
-        float *hk = ar.take<float>(g.nz + 1);
+        float *hk = ar.take<float>(layer_table_len(g.nz));
         double *upart = ar.take<double>((size_t)ap.nparts * g.nsegs());
         double *U = ar.take<double>(g.nsegs());
         if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the adjoint sweep");
@@ -175,7 +175,7 @@ int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double
     const ForwardPlan tp = plan_trace(g.nx, o.n);
     double *part = ar.take<double>((size_t)tp.nchunk * o.n);
     double *dg = diag ? diag : ar.take<double>(o.n);
-    float *hk = ar.take<float>(g.nz + 1);
+    float *hk = ar.take<float>(layer_table_len(g.nz));
     if (ar.failed) return fail(ctx, GRAV_ENOMEM, "workspace too small for the trace sweep");
     if (prec == GRAV_MIXED) {
         HIP_TRY(launch_layer_thickness(g, hk, st), "layer thickness");

@@ -55,6 +55,12 @@ struct Counter {
 constexpr int kBlock = 256;          // threads per block of the sweeps
 constexpr int kAdjLayers = 16;       // max layers per lane in the mixed adjoint sweep
 
+// Layer table of the mixed sweeps (floats): [0, nz) the layer thicknesses
+// h_k = Z_{k+1} - Z_k; [nz] (as an int) the first "deep" layer; [nz+1, 2nz+1)
+// the node depths below the mesh top Z_{k+1} - Z_0.  Each entry is an FP64
+// difference rounded once to FP32.
+inline size_t layer_table_len(int nz) { return 2 * (size_t)nz + 1; }
+
 // Forward sweep: lanes own observations; the mesh columns are split into
 // `nchunk` contiguous chunks, one per block row, with partial sums per chunk.
 struct ForwardPlan {

@@ -194,7 +194,7 @@ size_t request_layout(Request &q, char *base) {
     const Mesh &g = q.g;
     const int64_t n = q.o.n;
     q.fp = plan_forward(g.ncols(), n);
-    q.hk = ar.take<float>(g.nz + 1);
+    q.hk = ar.take<float>(layer_table_len(g.nz));
     q.w2 = ar.take<double>(g.nsegs());
     q.fpart = ar.take<double>((size_t)q.fp.nchunk * n);
     if (q.r.kind == GRAV_REQ_INVERT) {

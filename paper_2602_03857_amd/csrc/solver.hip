@@ -230,7 +230,7 @@ static size_t need_forward(const Mesh &g, int64_t n, grav_prec prec) {
     const ForwardPlan fp = plan_forward(g.ncols(), n);
     c.take<double>((size_t)fp.nchunk * n);
     if (prec == GRAV_MIXED) {
-        c.take<float>(g.nz + 1);
+        c.take<float>(layer_table_len(g.nz));
         c.take<double>(g.nsegs());
     } else {
         c.take<double>(g.nnodes());
@@ -242,7 +242,7 @@ static size_t need_adjoint(const Mesh &g, int64_t n, grav_prec prec) {
     Counter c;
     if (prec == GRAV_MIXED) {
         const AdjointPlan ap = plan_adjoint(g.ncols(), g.nz, n);
-        c.take<float>(g.nz + 1);
+        c.take<float>(layer_table_len(g.nz));
         c.take<double>((size_t)ap.nparts * g.nsegs());
         c.take<double>(g.nsegs());
     } else {
@@ -258,7 +258,7 @@ static size_t need_trace(const Mesh &g, int64_t n) {
     const ForwardPlan tp = plan_trace(g.nx, n);
     c.take<double>((size_t)tp.nchunk * n);
     c.take<double>(n);
-    c.take<float>(g.nz + 1);
+    c.take<float>(layer_table_len(g.nz));
     return c.off;
 }
 

@@ -8,6 +8,15 @@
 
 namespace grav {
 
+// Depth below the observation of node c of a column, Z_c - z_o, as the FP32 sum
+// of (Z_c - Z_0) from the layer table and ztop = Z_0 - z_o: both terms are
+// non-negative FP64 differences rounded to FP32, so the sum has no
+// cancellation (relative error below 2^-22), and every sweep forms the same
+// value for the same node.
+__device__ __forceinline__ float node_depth(const float *__restrict__ zrel, int c, float ztop) {
+    return c == 0 ? ztop : zrel[c - 1] + ztop;
+}
+
 // Forward sweep, one block: observations oblk*kBlock + [0, kBlock) against node
 // columns [chunk*cols_per_chunk, ...), writing partial[chunk*n + o] =
 // sum over the chunk's segments of S * W2 (FP64 accumulation).
@@ -24,6 +33,7 @@ __device__ __forceinline__ void forward_mixed_block(
     const int64_t c0 = (int64_t)chunk * cols_per_chunk;
     const int64_t c1 = c0 + cols_per_chunk < ncols ? c0 + cols_per_chunk : ncols;
     const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
+    const float *__restrict__ zrel = hk + nz + 1;
     double acc = 0.0;
     int a = (int)(c0 / ny1), b = (int)(c0 - (int64_t)a * ny1);
     for (int64_t col = c0; col < c1; ++col) {
@@ -33,14 +43,14 @@ __device__ __forceinline__ void forward_mixed_block(
         int k = 0;
 #pragma unroll 2
         for (; k < kdeep; ++k) {
-            const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
+            const Node bot = make_node(c, zrel[k] + ztop);
             const float S = edge_segment<false>(c, top, bot, hk[k]);
             acc = fma(static_cast<double>(S), w[k], acc);
             top = bot;
         }
 #pragma unroll 2
         for (; k < nz; ++k) {
-            const Node bot = make_node(c, static_cast<float>(zn[k + 1] - zo));
+            const Node bot = make_node(c, zrel[k] + ztop);
             const float S = edge_segment<true>(c, top, bot, hk[k]);
             acc = fma(static_cast<double>(S), w[k], acc);
             top = bot;
@@ -50,20 +60,21 @@ __device__ __forceinline__ void forward_mixed_block(
     if (o < n) partial[(int64_t)chunk * n + o] = acc;
 }
 
-// One observation's contribution to a lane's layer chunk of the adjoint.
-// kFull: the chunk has exactly kAdjLayers layers (no per-layer guard, so the
-// segments form one basic block the compiler can interleave).
-template <bool kDeep, bool kFull>
-__device__ __forceinline__ void adjoint_obs(double X, double Y, const double *__restrict__ zn, int k0,
-                                            int cnt, const float (&h)[kAdjLayers], double xo,
-                                            double yo, double zo, double vo,
-                                            double (&acc)[kAdjLayers]) {
+// One observation's contribution to a lane's layer chunk of the adjoint:
+// layers k0 .. k0 + cnt - 1 (cnt <= kAdjLayers; the guard on j < cnt is
+// uniform across the block).
+template <bool kDeep>
+__device__ __forceinline__ void adjoint_obs(double X, double Y, const float *__restrict__ zrel,
+                                            double zn0, int k0, int cnt,
+                                            const float (&h)[kAdjLayers], double xo, double yo,
+                                            double zo, double vo, double (&acc)[kAdjLayers]) {
     const Column c = make_column(X, Y, xo, yo);
-    Node top = make_node(c, static_cast<float>(zn[k0] - zo));
+    const float ztop = static_cast<float>(zn0 - zo);
+    Node top = make_node(c, node_depth(zrel, k0, ztop));
 #pragma unroll
     for (int j = 0; j < kAdjLayers; ++j) {
-        if (kFull || j < cnt) {
-            const Node bot = make_node(c, static_cast<float>(zn[k0 + j + 1] - zo));
+        if (j < cnt) {
+            const Node bot = make_node(c, zrel[k0 + j] + ztop);
             const float S = edge_segment<kDeep>(c, top, bot, h[j]);
             acc[j] = fma(vo, static_cast<double>(S), acc[j]);
             top = bot;
@@ -71,9 +82,9 @@ __device__ __forceinline__ void adjoint_obs(double X, double Y, const double *__
     }
 }
 
-// Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane, layer
-// chunk kc (layers kc*kAdjLayers ..., the last chunk may be shorter),
-// observations of part `part`;
+// Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane and
+// layer chunk kc of nkc (nkc = ceil(nz / kAdjLayers) chunks of near-equal
+// length, at most kAdjLayers layers each), observations of part `part`;
 // writes upart[part][segment] = sum_{o in part} v_o S (FP64, one register
 // pair per layer, no cross-lane reduction).
 __device__ __forceinline__ void adjoint_mixed_block(
@@ -87,8 +98,10 @@ __device__ __forceinline__ void adjoint_mixed_block(
     const int a = (int)(colc / ny1);
     const int b = (int)(colc - (int64_t)a * ny1);
     const double X = xn[a], Y = yn[b];
-    const int k0 = kc * kAdjLayers;
-    const int cnt = nz - k0 < kAdjLayers ? nz - k0 : kAdjLayers;
+    const int k0 = (int)((int64_t)kc * nz / nkc);
+    const int cnt = (int)((int64_t)(kc + 1) * nz / nkc) - k0;
+    const float *__restrict__ zrel = hk + nz + 1;
+    const double zn0 = zn[0];
     float h[kAdjLayers];
 #pragma unroll
     for (int j = 0; j < kAdjLayers; ++j) h[j] = j < cnt ? hk[k0 + j] : 1.0f;
@@ -98,22 +111,12 @@ __device__ __forceinline__ void adjoint_mixed_block(
     const int64_t o0 = (int64_t)part * obs_per_part;
     const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
     const bool deep = k0 >= reinterpret_cast<const int *>(hk + nz)[0];   // uniform per block
-    if (cnt == kAdjLayers) {
-        if (deep) {
-            for (int64_t o = o0; o < o1; ++o)
-                adjoint_obs<true, true>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
-        } else {
-            for (int64_t o = o0; o < o1; ++o)
-                adjoint_obs<false, true>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
-        }
+    if (deep) {
+        for (int64_t o = o0; o < o1; ++o)
+            adjoint_obs<true>(X, Y, zrel, zn0, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
     } else {
-        if (deep) {
-            for (int64_t o = o0; o < o1; ++o)
-                adjoint_obs<true, false>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
-        } else {
-            for (int64_t o = o0; o < o1; ++o)
-                adjoint_obs<false, false>(X, Y, zn, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
-        }
+        for (int64_t o = o0; o < o1; ++o)
+            adjoint_obs<false>(X, Y, zrel, zn0, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
     }
     if (col < ncols) {
         double *__restrict__ dst = upart + (int64_t)part * ncols * nz + col * nz + k0;

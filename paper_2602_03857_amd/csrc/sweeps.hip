@@ -33,12 +33,16 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 
 // ------------------------------------------------------------------ O(M)
 
-// Layer table: hk[k] = thickness of layer k (FP32), and after it (as an int)
-// the first layer index from which every layer is "deep" (its top at least
-// kDeepRatio thicknesses below the mesh top).
+// Layer table (layout at layer_table_len): hk[k] = thickness of layer k,
+// then (as an int) the first layer index from which every layer is "deep"
+// (its top at least kDeepRatio thicknesses below the mesh top), then the
+// node depths Z_{k+1} - Z_0.
 __global__ void k_layer_thickness(const double *__restrict__ zn, int nz, float *__restrict__ hk) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nz) hk[k] = static_cast<float>(zn[k + 1] - zn[k]);
+    if (k < nz) {
+        hk[k] = static_cast<float>(zn[k + 1] - zn[k]);
+        hk[nz + 1 + k] = static_cast<float>(zn[k + 1] - zn[0]);
+    }
     if (k == 0) {
         int kdeep = nz;
         while (kdeep > 0 && (zn[kdeep - 1] - zn[0]) >= kDeepRatio * (zn[kdeep] - zn[kdeep - 1])) --kdeep;
@@ -257,12 +261,14 @@ __global__ __launch_bounds__(kBlock) void k_trace_mixed(
     const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
     const int i0 = (int)(chunk * rows_per_chunk);
     const int i1 = (int)(i0 + rows_per_chunk < nx ? i0 + rows_per_chunk : nx);
+    const float ztop = static_cast<float>(zn[0] - zo);
+    const float *__restrict__ zrel = hk + nz + 1;
     double acc = 0.0;
     for (int i = i0; i < i1; ++i) {
         const double Xa = xn[i], Xb = xn[i + 1];
         for (int k = 0; k < nz; ++k) {
-            const float z1 = static_cast<float>(zn[k] - zo);
-            const float z2 = static_cast<float>(zn[k + 1] - zo);
+            const float z1 = node_depth(zrel, k, ztop);
+            const float z2 = node_depth(zrel, k + 1, ztop);
             const float h = hk[k];
             Column ca = make_column(Xa, yn[0], xo, yo);
             Column cb = make_column(Xb, yn[0], xo, yo);
