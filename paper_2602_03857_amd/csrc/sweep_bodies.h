@@ -40,19 +40,37 @@ __device__ __forceinline__ void forward_mixed_block(
         const Column c = make_column(xn[a], yn[b], xo, yo);
         Node top = make_node(c, ztop);
         const double *__restrict__ w = w2 + col * nz;
+        // The layer constants (edge weight, thickness, node depth) are
+        // wave-uniform scalar loads.  Used as soon as they are loaded, each
+        // layer would wait on a scalar-cache round trip; instead they run
+        // through a two-deep pipeline: layer k's values were loaded while
+        // layers k-2 and k-1 were computed (indices clamped at the last layer,
+        // so no load leaves the column).
         int k = 0;
-#pragma unroll 2
+        double w_a = w[0], w_b = w[nz > 1 ? 1 : 0];
+        float h_a = hk[0], z_a = zrel[0], h_b = hk[nz > 1 ? 1 : 0], z_b = zrel[nz > 1 ? 1 : 0];
+#pragma unroll 8
         for (; k < kdeep; ++k) {
-            const Node bot = make_node(c, zrel[k] + ztop);
-            const float S = edge_segment<false>(c, top, bot, hk[k]);
-            acc = fma(static_cast<double>(S), w[k], acc);
+            const int kn = k + 2 < nz ? k + 2 : nz - 1;
+            const double wc = w_a;
+            const float hc = h_a, zc = z_a;
+            w_a = w_b; h_a = h_b; z_a = z_b;
+            w_b = w[kn]; h_b = hk[kn]; z_b = zrel[kn];
+            const Node bot = make_node(c, zc + ztop);
+            const float S = edge_segment<false>(c, top, bot, hc);
+            acc = fma(static_cast<double>(S), wc, acc);
             top = bot;
         }
-#pragma unroll 2
+#pragma unroll 8
         for (; k < nz; ++k) {
-            const Node bot = make_node(c, zrel[k] + ztop);
-            const float S = edge_segment<true>(c, top, bot, hk[k]);
-            acc = fma(static_cast<double>(S), w[k], acc);
+            const int kn = k + 2 < nz ? k + 2 : nz - 1;
+            const double wc = w_a;
+            const float hc = h_a, zc = z_a;
+            w_a = w_b; h_a = h_b; z_a = z_b;
+            w_b = w[kn]; h_b = hk[kn]; z_b = zrel[kn];
+            const Node bot = make_node(c, zc + ztop);
+            const float S = edge_segment<true>(c, top, bot, hc);
+            acc = fma(static_cast<double>(S), wc, acc);
             top = bot;
         }
         if (++b == ny1) { b = 0; ++a; }
