@@ -250,9 +250,12 @@ int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of forward and inversion requests on one GPU
  * (GRAV_MIXED precision).  A worker thread owns a device memory pool of
- * `budget_bytes`; queued requests are admitted in arrival order while their
- * state (O(N + M) per request: partial sums, CG vectors) fits in the pool and
- * fewer than `max_active` are in flight.  Every scheduling step issues one
+ * `budget_bytes`; queued requests are admitted while their state (O(N + M)
+ * per request: partial sums, CG vectors) fits in the pool: inversions in
+ * arrival order while fewer than `max_active` are in flight, forward requests
+ * (one step each) in arrival order on `max_active` slots of their own, passing
+ * inversions that wait only for an inversion slot (never one that waits for
+ * pool memory, so no request starves).  Every scheduling step issues one
  * batched launch per sweep type that covers the blocks of all active
  * requests, so each active inversion advances one CG iteration per step and
  * requests that arrive meanwhile join at the next step.  A request's launch
@@ -266,7 +269,8 @@ typedef enum { GRAV_REQ_FORWARD = 0, GRAV_REQ_INVERT = 1 } grav_req_kind;
 
 typedef struct {
     int32_t device;         /* HIP device ordinal */
-    int32_t max_active;     /* requests in flight at once; 0 = 64 (max 256) */
+    int32_t max_active;     /* inversions in flight at once, and as many forward
+                               requests; 0 = 64 (max 256) */
     uint64_t budget_bytes;  /* device memory for request state; 0 = 16 GiB */
 } grav_server_opts;
 

@@ -1,8 +1,11 @@
 // Continuous-batching server for forward and inversion requests (declared in
 // include/grav.h).  One worker thread per server runs scheduling steps:
 //
-//   admit   queued requests (arrival order) while their state fits in the
-//           device pool and fewer than max_active are in flight;
+//   admit   queued requests while their state fits in the device pool:
+//           inversions in arrival order while fewer than max_active are in
+//           flight; forward requests (one step each) in arrival order on
+//           their own max_active slots, passing inversions that wait only
+//           for an inversion slot (never one that waits for pool memory);
 //   init    per newly admitted request: layer thicknesses, W2(m) (forward) or
 //           trace -> lambda, r = p = d_obs, y = 0, r.r (inversion);
 //   sweep A one persistent batched adjoint launch over every inversion in CG
@@ -224,11 +227,12 @@ struct grav_server {
     char *pool = nullptr;
     size_t pool_bytes = 0;
     PoolAllocator *alloc = nullptr;
-    double *scal_dev = nullptr;      // [max_active][kSlotScalars]
+    // Slots: [0, max_active) inversions, [max_active, 2 max_active) forwards.
+    double *scal_dev = nullptr;      // [2 max_active][kSlotScalars]
     double *scal_host = nullptr;     // pinned mirror
-    FwdJob *fjobs_dev = nullptr, *fjobs_host = nullptr;
-    AdjJob *ajobs_dev = nullptr, *ajobs_host = nullptr;
-    std::vector<int> free_slots;
+    FwdJob *fjobs_dev = nullptr, *fjobs_host = nullptr;   // 2 max_active entries
+    AdjJob *ajobs_dev = nullptr, *ajobs_host = nullptr;   // max_active entries
+    std::vector<int> free_inv_slots, free_fwd_slots;
     grav_ctx *vctx = nullptr;        // validation of submitted requests
     std::mutex vmu;
 
@@ -380,15 +384,25 @@ void grav_server::run() {
     for (;;) {
         cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
         if (stop && queue.empty() && active.empty()) break;
-        // admission: arrival order, by pool memory and slot count
-        while (!queue.empty() && (int)active.size() < max_active) {
-            Request *q = queue.front();
+        // admission (see the policy at the top of this file)
+        bool inv_blocked = false;
+        for (auto it = queue.begin(); it != queue.end();) {
+            Request *q = *it;
+            const bool fwd = q->r.kind == GRAV_REQ_FORWARD;
+            std::vector<int> &slots = fwd ? free_fwd_slots : free_inv_slots;
+            if (slots.empty()) {
+                if (fwd) break;                 // forwards keep their order
+                inv_blocked = true;             // forwards behind may pass
+                ++it;
+                continue;
+            }
+            if (!fwd && inv_blocked) { ++it; continue; }
             size_t off = 0;
-            if (!alloc->alloc(q->bytes, &off)) break;
-            queue.pop_front();
+            if (!alloc->alloc(q->bytes, &off)) break;   // memory: strict arrival order
+            it = queue.erase(it);
             q->off = off;
-            q->slot = free_slots.back();
-            free_slots.pop_back();
+            q->slot = slots.back();
+            slots.pop_back();
             request_layout(*q, pool + off);
             q->phase = Phase::Init;
             q->t_admit = Clock::now();
@@ -411,7 +425,7 @@ void grav_server::run() {
         for (Request *q : active) {
             if (q->finished) {
                 alloc->release(q->off, q->bytes);
-                free_slots.push_back(q->slot);
+                (q->r.kind == GRAV_REQ_FORWARD ? free_fwd_slots : free_inv_slots).push_back(q->slot);
                 q->done = true;
             } else {
                 still.push_back(q);
@@ -459,15 +473,16 @@ extern "C" int grav_server_create(grav_server **out, const grav_server_opts *opt
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->vstream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->pool), s->pool_bytes);
+    const size_t nslots = 2 * (size_t)s->max_active;
     if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void **>(&s->scal_dev), (size_t)s->max_active * kSlotScalars * sizeof(double));
+        e = hipMalloc(reinterpret_cast<void **>(&s->scal_dev), nslots * kSlotScalars * sizeof(double));
     if (e == hipSuccess)
-        e = hipMemset(s->scal_dev, 0, (size_t)s->max_active * kSlotScalars * sizeof(double));
+        e = hipMemset(s->scal_dev, 0, nslots * kSlotScalars * sizeof(double));
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void **>(&s->scal_host), (size_t)s->max_active * kSlotScalars * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->fjobs_dev), (size_t)s->max_active * sizeof(FwdJob));
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->scal_host), nslots * kSlotScalars * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->fjobs_dev), nslots * sizeof(FwdJob));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->ajobs_dev), (size_t)s->max_active * sizeof(AdjJob));
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->fjobs_host), (size_t)s->max_active * sizeof(FwdJob), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->fjobs_host), nslots * sizeof(FwdJob), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->ajobs_host), (size_t)s->max_active * sizeof(AdjJob), hipHostMallocDefault);
     if (e != hipSuccess) {
         const bool oom = e == hipErrorOutOfMemory;
@@ -485,7 +500,8 @@ extern "C" int grav_server_create(grav_server **out, const grav_server_opts *opt
         return oom ? GRAV_ENOMEM : GRAV_EDEVICE;
     }
     s->alloc = new PoolAllocator(s->pool_bytes);
-    for (int i = s->max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
+    for (int i = s->max_active - 1; i >= 0; --i) s->free_inv_slots.push_back(i);
+    for (int i = 2 * s->max_active - 1; i >= s->max_active; --i) s->free_fwd_slots.push_back(i);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return GRAV_OK;

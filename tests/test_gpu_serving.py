@@ -134,3 +134,25 @@ def test_bad_requests_rejected(g):
         t = srv.submit_forward(mesh, obs, _t(p.m), d)
         srv.wait(t)
         assert rel_l2(to_np(d), prism.forward(p.mesh, p.obs, p.m)) <= 1e-5
+
+
+def test_forward_requests_pass_inversions_waiting_for_a_slot(g):
+    """With one inversion slot, a forward request submitted behind a queued
+    inversion is served while the first inversion runs; the queued inversion
+    starts only when the slot frees."""
+    cases = _requests()
+    (ka, pa), (kc, pc), (kb, pb) = cases[0], cases[1], cases[2]
+    assert (ka, kc, kb) == ("inv", "fwd", "inv")
+    with g.Server(0, max_active=1, budget_bytes=1 << 30) as srv:
+        da, db, dc = (_device_problem(g, k, p) for k, p in ((ka, pa), (kb, pb), (kc, pc)))
+        ta = _submit(srv, ka, da)
+        tb = _submit(srv, kb, db)
+        tc = _submit(srv, kc, dc)
+        ia, ib, ic = srv.wait(ta), srv.wait(tb), srv.wait(tc)
+    print(f"[serving] one slot: A run {ia['run_ms']:.1f} ms, B queue {ib['queue_ms']:.1f} ms, "
+          f"C queue {ic['queue_ms']:.1f} ms run {ic['run_ms']:.1f} ms", flush=True)
+    assert ia["iters"] > 10
+    # C finished before A did; B waited for A's slot
+    assert ic["queue_ms"] + ic["run_ms"] < ia["queue_ms"] + ia["run_ms"]
+    assert ib["queue_ms"] >= 0.9 * (ia["queue_ms"] + ia["run_ms"])
+    assert rel_l2(_result(kc, dc), prism.forward(pc.mesh, pc.obs, pc.m)) <= 1e-5
