@@ -156,3 +156,44 @@ def test_forward_requests_pass_inversions_waiting_for_a_slot(g):
     assert ic["queue_ms"] + ic["run_ms"] < ia["queue_ms"] + ia["run_ms"]
     assert ib["queue_ms"] >= 0.9 * (ia["queue_ms"] + ia["run_ms"])
     assert rel_l2(_result(kc, dc), prism.forward(pc.mesh, pc.obs, pc.m)) <= 1e-5
+
+
+def test_serving_stream_largest_requests_sampled():
+    """The largest forward request of the serving stream (about 40k stations
+    over about 800k cells) served in a mix with stream inversions: its data
+    match the FP64 oracle on sampled stations, and the inversions finish."""
+    import torch
+    pkg = load_package()
+    reqs = workloads.config5_stream()
+    fwd = max((r for r in reqs if r["kind"] == "forward"),
+              key=lambda r: r["n_target"] * r["cells_target"])
+    invs = sorted((r for r in reqs if r["kind"] == "inversion"),
+                  key=lambda r: r["n_target"] * r["cells_target"])[:3]
+    pf = fwd["build"]()
+    print(f"[serving] largest forward: {pf.obs.n} stations x {pf.mesh.ncells} cells", flush=True)
+    mesh, obs = pkg.DeviceMesh.from_mesh(pf.mesh), pkg.DeviceObs.from_survey(pf.obs)
+    d = torch.empty(pf.obs.n, dtype=torch.float64, device="cuda")
+    with pkg.Server(0, budget_bytes=8 << 30) as srv:
+        items = []
+        for r in invs:
+            p = r["build"]()
+            dm, do = pkg.DeviceMesh.from_mesh(p.mesh), pkg.DeviceObs.from_survey(p.obs)
+            d_obs = _t(inversion.add_noise(prism.forward(p.mesh, p.obs, p.m), p.noise_draws,
+                                           p.noise_level))
+            m_out = torch.empty(p.mesh.ncells, dtype=torch.float64, device="cuda")
+            items.append((dm, do, d_obs, m_out))
+            srv_t = srv.submit_invert(dm, do, d_obs, _t(p.wdepth), m_out, lam=-1.0,
+                                      tol=p.cg_tol, max_iter=p.cg_iters)
+            items[-1] += (srv_t,)
+        tf = srv.submit_forward(mesh, obs, _t(pf.m), d)
+        info_f = srv.wait(tf)
+        infos = [srv.wait(it[-1]) for it in items]
+    rows = np.sort(np.random.default_rng(55).choice(pf.obs.n, 16, replace=False))
+    ref = prism.forward(pf.mesh, pf.obs, pf.m, rows)
+    err = rel_l2(to_np(d)[rows], ref)
+    print(f"[serving] largest forward, 16 sampled stations: rel L2 = {err:.3e}; inversions "
+          f"{[i['iters'] for i in infos]} iterations, status {[i['status'] for i in infos]}",
+          flush=True)
+    assert info_f["status"] == 0 and err <= 1e-5
+    assert all(i["status"] in (0, 4) for i in infos)
+    assert all(np.all(np.isfinite(to_np(it[3]))) for it in items)
