@@ -297,6 +297,22 @@ def run_cg_full(args) -> int:
     return 0
 
 
+def run_issue_probe(args) -> int:
+    """Measure the issue rates behind the roofline's slot weights."""
+    import torch  # noqa: F401
+    import paper_2602_03857_amd as g
+    with g.Context(0) as ctx:
+        r = ctx.issue_rates()
+    fma = r["fma32"]
+    out = {"metric": "gfx950 issue rates (chain steps/s summed over lanes)", "rates": r,
+           "fma32_per_peak_slot": fma / PEAK_SLOTS,
+           "slots_per_instruction": {k: (fma / r[k] - 1.0 if k in ("log", "rcp", "sqrt")
+                                         else fma / r[k]) for k in r},
+           "weights_used": {"transcendental": TRANS_COST, "fp64": FP64_COST}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +327,8 @@ def main() -> int:
     ap.add_argument("--serve", action="store_true", help="replay the serving stream instead")
     ap.add_argument("--cg-full", action="store_true",
                     help="time the paper-scale 50-iteration CG solve instead")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="measure the instruction issue rates behind the roofline weights")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -329,6 +347,8 @@ def main() -> int:
         return run_serve(args)
     if args.cg_full:
         return run_cg_full(args)
+    if args.issue_probe:
+        return run_issue_probe(args)
     if args.copy_probe:
         import torch
         nbytes = args.copy_probe << 20
@@ -354,8 +374,13 @@ def main() -> int:
 
     lib_path = os.path.join(ROOT, "paper_2602_03857_amd", "libgrav.so")
     if not os.path.exists(lib_path):
-        from paper_2602_03857_amd.build import build
-        build()
+        # by path: importing the package would try to load the missing library
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "grav_build", os.path.join(ROOT, "paper_2602_03857_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
     import torch
     import paper_2602_03857_amd as g
 

@@ -4,7 +4,7 @@ Argument marshalling only: every step of every operator runs in the HIP
 kernels behind the C ABI declared in ``include/grav.h``.  PyTorch provides
 device memory and streams.  Importing this module loads the in-tree
 ``libgrav.so`` and raises ``ImportError`` when it has not been built
-(``python -m paper_2602_03857_amd.build``); there is no CPU fallback.
+(``python paper_2602_03857_amd/build.py``); there is no CPU fallback.
 """
 from __future__ import annotations
 

@@ -73,7 +73,7 @@ def _load():
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -m paper_2602_03857_amd.build` "
+            f"{LIB_PATH} is missing: build it with `python paper_2602_03857_amd/build.py` "
             "(the gravity operators have no CPU fallback)")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
@@ -102,6 +102,7 @@ def _load():
         "grav_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, P(RequestInfo)]),
         "grav_server_destroy": (None, [vp]),
         "grav_set_timing": (ctypes.c_int, [vp, i32]),
+        "grav_issue_rates": (ctypes.c_int, [vp, P(dbl), vp]),
         "grav_kernel_time": (ctypes.c_int, [vp, ctypes.c_char_p, P(dbl), P(i64)]),
         "grav_reset_timing": (ctypes.c_int, [vp]),
     }
@@ -119,6 +120,6 @@ EXPORTED = [
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
     "grav_trend_surface",
     "grav_invert", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
-    "grav_reset_timing", "grav_server_create", "grav_server_submit", "grav_server_poll",
+    "grav_reset_timing", "grav_issue_rates", "grav_server_create", "grav_server_submit", "grav_server_poll",
     "grav_server_wait", "grav_server_destroy",
 ]

@@ -1,6 +1,8 @@
 """Build the HIP library ``libgrav.so`` in-tree for gfx950 with hipcc.
 
-Usage: ``python -m paper_2602_03857_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_2602_03857_amd/build.py`` (run as a file: importing the
+package would load the library it builds), or ``build()`` of this module
+loaded by path.
 Every call recompiles all sources (one hipcc process per translation unit,
 run in parallel) and links the shared library next to this file.
 """
@@ -18,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgrav.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "sweeps.hip", "vec.hip", "solver.hip", "multi.hip", "server.hip", "trend.hip"]
+SOURCES = ["api.hip", "sweeps.hip", "vec.hip", "solver.hip", "multi.hip", "server.hip", "trend.hip", "probe.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.

@@ -359,6 +359,12 @@ extern "C" int grav_trace(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *
     return op_trace(ctx, ar, g, o, wdepth, trace, diag, prec, st);
 }
 
+extern "C" int grav_issue_rates(grav_ctx *ctx, double *rates, grav_stream stream) {
+    ENTER(ctx);
+    if (!rates) return fail(ctx, GRAV_EINVAL, "rates is NULL");
+    return grav::op_issue_rates(ctx, rates, reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" int grav_trend_surface(grav_ctx *ctx, const double *x, const double *y, const double *v,
                                   int64_t n, int32_t degree, double *coef, double *frame,
                                   double *resid, double *trend, grav_stream stream) {

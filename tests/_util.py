@@ -13,8 +13,13 @@ def load_package():
     """Import the binding, building libgrav.so first only if it is absent."""
     lib = os.path.join(ROOT, "paper_2602_03857_amd", "libgrav.so")
     if not os.path.exists(lib):
-        from paper_2602_03857_amd.build import build
-        build()
+        # by path: importing the package would try to load the missing library
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "grav_build", os.path.join(ROOT, "paper_2602_03857_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
     import paper_2602_03857_amd as g
     return g
 

@@ -3,6 +3,7 @@ declares; host-only calls behave (no compute calls: CPU only)."""
 import ctypes
 import os
 import re
+import sys
 import subprocess
 
 import pytest
@@ -69,3 +70,16 @@ def test_opts_default():
     o = g.CtxOpts()
     g.lib.grav_ctx_opts_default(ctypes.byref(o))
     assert o.device == 0 and o.validate == 1 and o.workspace_bytes == 0
+
+
+def test_build_module_loads_without_the_library():
+    """The build entry must work on a checkout without libgrav.so: its build
+    module is loaded by path and must not import the package (which loads the
+    library)."""
+    import subprocess
+    code = ("import sys, __graft_entry__ as e; m = e._build_module(); "
+            "assert 'paper_2602_03857_amd' not in sys.modules; "
+            "assert 'probe.hip' in m.SOURCES and callable(m.build); print('ok')")
+    res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=120)
+    assert res.returncode == 0 and res.stdout.strip() == "ok", res.stderr
