@@ -38,13 +38,14 @@ import workloads  # noqa: E402
 # edge-segment formula (per-operation table in the design notes), 94
 # instructions for layers near the top and 84 for "deep" layers (top at least
 # 9 thicknesses below the mesh top, where the atan difference needs no range
-# reduction).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log; measured to
-# issue at 1/4 of the FMA rate) and 2 are FP64 (half rate); issue slots per
-# pair = instructions + 3 * 6 + 1 * 2.
+# reduction).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log) and 2 are
+# FP64.  Issue cost relative to an FP32 add, measured with --issue-probe
+# (dependent chains of one instruction class): a transcendental takes 2 slots,
+# an FP64 FMA 1; issue slots per pair = instructions + 6 * (2 - 1).
 PEAK_SLOTS = 157.3e12 / 2.0
 INSTR_SHALLOW, INSTR_DEEP = 94, 84
 N_TRANS, N_FP64 = 6, 2
-TRANS_COST, FP64_COST = 4, 2
+TRANS_COST, FP64_COST = 2, 1
 DEEP_RATIO = 9.0
 
 
@@ -306,7 +307,7 @@ def run_issue_probe(args) -> int:
     fma = r["fma32"]
     out = {"metric": "gfx950 issue rates (chain steps/s summed over lanes)", "rates": r,
            "fma32_per_peak_slot": fma / PEAK_SLOTS,
-           "slots_per_instruction": {k: (fma / r[k] - 1.0 if k in ("log", "rcp", "sqrt")
+           "slots_per_instruction": {k: (fma / r[k] - fma / r["add32"] if k in ("log", "rcp", "sqrt")
                                          else fma / r[k]) for k in r},
            "weights_used": {"transcendental": TRANS_COST, "fp64": FP64_COST}}
     print(json.dumps(out), flush=True)

@@ -337,11 +337,12 @@ int grav_set_timing(grav_ctx *ctx, int32_t enable);
 
 /* Diagnostics: sustained issue rates of the instruction classes the sweeps
  * are built from, measured on the context's device with eight independent
- * dependency chains per lane and eight waves per SIMD.  rates (HOST, 5
+ * dependency chains per lane and eight waves per SIMD.  rates (HOST, 6
  * doubles) receives chain steps per second summed over lanes for:
  *   [0] FP32 FMA, [1] v_log_f32 + FP32 add, [2] v_rcp_f32 + FP32 add,
- *   [3] v_sqrt_f32 + FP32 add, [4] FP64 FMA.
- * A transcendental's cost in FP32-FMA issue slots is rates[0]/rates[i] - 1.
+ *   [3] v_sqrt_f32 + FP32 add, [4] FP64 FMA, [5] FP32 add.
+ * A transcendental's cost in FP32-FMA issue slots is
+ * rates[0]/rates[i] - rates[0]/rates[5].
  * Runs about 20 ms of device work; waits for it.
  * Errors: GRAV_EINVAL (null ctx/rates), GRAV_ENOMEM, GRAV_EDEVICE. */
 int grav_issue_rates(grav_ctx *ctx, double *rates, grav_stream stream);

@@ -192,10 +192,10 @@ class Context:
     def issue_rates(self, stream=None):
         """Measured issue rates of the sweeps' instruction classes (chain steps
         per second summed over lanes): fma32, log, rcp, sqrt (each + an FP32
-        add), fma64."""
-        r = (ctypes.c_double * 5)()
+        add), fma64, add32."""
+        r = (ctypes.c_double * 6)()
         self._rc(lib.grav_issue_rates(self._h, r, self._stream(stream)))
-        return dict(zip(("fma32", "log", "rcp", "sqrt", "fma64"), list(r)))
+        return dict(zip(("fma32", "log", "rcp", "sqrt", "fma64", "add32"), list(r)))
 
     def trend_surface(self, x, y, v, degree=2, resid=None, trend=None, stream=None):
         """Least-squares trend surface of `degree` (1 or 2) through (x, y, v)

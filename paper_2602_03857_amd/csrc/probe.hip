@@ -15,18 +15,26 @@ namespace {
 constexpr int kProbeIters = 2048;
 constexpr int kProbeChains = 8;
 
-enum ProbeOp { kOpFma32 = 0, kOpLog = 1, kOpRcp = 2, kOpSqrt = 3, kOpFma64 = 4, kNumProbeOps = 5 };
+enum ProbeOp {
+    kOpFma32 = 0, kOpLog = 1, kOpRcp = 2, kOpSqrt = 3, kOpFma64 = 4, kOpAdd32 = 5, kNumProbeOps = 6
+};
 
+// Every chain step is one short (4-byte) instruction: the FMA chains add k*b
+// with k in a scalar register (v_fmac), the transcendental chains add an
+// inline constant; the step loop is unrolled so scalar loop control is rare.
 template <int OP>
-__global__ __launch_bounds__(256) void k_issue_rate(float *__restrict__ out, int iters) {
+__global__ __launch_bounds__(256) void k_issue_rate(float *__restrict__ out, int iters, float k,
+                                                    double k64) {
     const float s = 1.1f + threadIdx.x * 1e-3f;
     if constexpr (OP == kOpFma64) {
         double a[kProbeChains];
+        const double b = 1e-9 * s;
 #pragma unroll
         for (int c = 0; c < kProbeChains; ++c) a[c] = s + 0.1 * c;
+#pragma unroll 4
         for (int i = 0; i < iters; ++i) {
 #pragma unroll
-            for (int c = 0; c < kProbeChains; ++c) a[c] = fma(a[c], 1.0000000001, 1e-12);
+            for (int c = 0; c < kProbeChains; ++c) a[c] = fma(k64, b, a[c]);
         }
         double r = 0.0;
 #pragma unroll
@@ -34,15 +42,18 @@ __global__ __launch_bounds__(256) void k_issue_rate(float *__restrict__ out, int
         out[blockIdx.x * blockDim.x + threadIdx.x] = static_cast<float>(r);
     } else {
         float a[kProbeChains];
+        const float b = 1e-7f * s;
 #pragma unroll
         for (int c = 0; c < kProbeChains; ++c) a[c] = s + 0.1f * c;
+#pragma unroll 4
         for (int i = 0; i < iters; ++i) {
 #pragma unroll
             for (int c = 0; c < kProbeChains; ++c) {
-                if constexpr (OP == kOpFma32) a[c] = fmaf(a[c], 1.0000001f, 1e-7f);
+                if constexpr (OP == kOpFma32) a[c] = fmaf(k, b, a[c]);
                 if constexpr (OP == kOpLog) a[c] = __builtin_amdgcn_logf(a[c]) + 2.0f;
-                if constexpr (OP == kOpRcp) a[c] = __builtin_amdgcn_rcpf(a[c]) + 1.5f;
+                if constexpr (OP == kOpRcp) a[c] = __builtin_amdgcn_rcpf(a[c]) + 2.0f;
                 if constexpr (OP == kOpSqrt) a[c] = __builtin_amdgcn_sqrtf(a[c]) + 1.0f;
+                if constexpr (OP == kOpAdd32) a[c] = a[c] + k;
             }
         }
         float r = 0.0f;
@@ -54,16 +65,16 @@ __global__ __launch_bounds__(256) void k_issue_rate(float *__restrict__ out, int
 
 template <int OP>
 hipError_t launch_probe(float *out, int blocks, hipStream_t st) {
-    k_issue_rate<OP><<<blocks, 256, 0, st>>>(out, kProbeIters);
+    k_issue_rate<OP><<<blocks, 256, 0, st>>>(out, kProbeIters, 0.999f, 0.999);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Rates in chain steps per lane per second, summed over lanes.  An FMA step is
-// one instruction; a transcendental step is the transcendental plus the FP32
-// add that keeps its chain going, so its issue cost in FMA slots is
-// rate(FMA32) / rate(step) - 1.
+// Rates in chain steps per lane per second, summed over lanes.  An FMA or add
+// step is one instruction; a transcendental step is the transcendental plus
+// the FP32 add that keeps its chain going, so its issue cost in FMA slots is
+// rate(FMA32) / rate(step) - rate(FMA32) / rate(add).
 int op_issue_rates(grav_ctx *ctx, double *rates, hipStream_t st) {
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -79,7 +90,7 @@ int op_issue_rates(grav_ctx *ctx, double *rates, hipStream_t st) {
     }
     hipError_t (*launchers[kNumProbeOps])(float *, int, hipStream_t) = {
         launch_probe<kOpFma32>, launch_probe<kOpLog>, launch_probe<kOpRcp>,
-        launch_probe<kOpSqrt>, launch_probe<kOpFma64>};
+        launch_probe<kOpSqrt>, launch_probe<kOpFma64>, launch_probe<kOpAdd32>};
     const double lane_ops = (double)blocks * 256 * kProbeIters * kProbeChains;
     int rc = GRAV_OK;
     for (int op = 0; op < kNumProbeOps && rc == GRAV_OK; ++op) {
