@@ -64,7 +64,7 @@ def first_deep_layer(zn) -> int:
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_mixed_config4_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_03857_amd", "csrc", f)
-                  for f in ("sweeps.hip", "sweep_bodies.h", "edge_math.h")]
+                  for f in ("sweeps.hip", "sweep_bodies.h", "edge_math.h", "grav_internal.h")]
 
 
 def kernel_source_hash() -> str:

@@ -52,7 +52,7 @@ struct Counter {
 
 // ---- launch plans -------------------------------------------------------
 
-constexpr int kBlock = 256;          // threads per block of the sweeps
+constexpr int kBlock = 128;          // threads per block of the sweeps (2 waves)
 constexpr int kAdjLayers = 16;       // max layers per lane in the mixed adjoint sweep
 
 // Layer table of the mixed sweeps (floats): [0, nz) the layer thicknesses

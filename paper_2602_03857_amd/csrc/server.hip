@@ -49,7 +49,8 @@ constexpr int kMaxActiveCap = 256;
 constexpr int kSlotScalars = 16;     // per active request in the device scalar table
 constexpr int kLambdaSlot = 6;       // lambda used by the request
 constexpr int kTraceSlot = 7;        // trace(G C G^T) when computed
-constexpr unsigned kPersistentBlocks = 2048;
+// Persistent batched grids: 8 resident waves on each of the 1024 SIMDs.
+constexpr unsigned kPersistentBlocks = 8 * 1024 / (kBlock / 64);
 
 struct FwdJob {
     const double *xn, *yn, *zn, *ox, *oy, *oz, *w2;
