@@ -8,20 +8,22 @@
 //           for an inversion slot (never one that waits for pool memory);
 //   init    per newly admitted request: layer thicknesses, W2(m) (forward) or
 //           trace -> lambda, r = p = d_obs, y = 0, r.r (inversion);
-//   sweep A one persistent batched adjoint launch over every inversion in CG
+//   sweep A one batched adjoint launch over every inversion in CG
 //           (v = p) or in its final step (v = y);
 //   post A  per request: reduce U, finish (x C, gamma) -> t and W2(t), or m_out;
-//   sweep F one persistent batched forward launch over every new forward
+//   sweep F one batched forward launch over every new forward
 //           request and every inversion in CG;
 //   post F  per request: d = gamma sum (forward) or the CG update
 //           q = gamma sum + lambda p, alpha, y, r, beta, p;
 //   sync    one copy of the CG scalar table, then the host advances each
 //           request (converged / max_iter -> final step; final -> done).
 //
-// A batched launch walks a table of per-request jobs (each with its own plan
-// and buffers) with a grid-stride loop over "virtual blocks"; a virtual block
-// runs the same per-block body as the single-call kernels, so a request's
-// arithmetic does not depend on what it is batched with.
+// A batched launch covers the blocks of every request in one grid: block b
+// finds its request in a table of per-request jobs (each with its own plan and
+// buffers, blocks numbered consecutively) and runs the same per-block body as
+// the single-call kernels, so a request's arithmetic does not depend on what
+// it is batched with, and the hardware dispatcher balances blocks of uneven
+// cost across the GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,8 +51,8 @@ constexpr int kMaxActiveCap = 256;
 constexpr int kSlotScalars = 16;     // per active request in the device scalar table
 constexpr int kLambdaSlot = 6;       // lambda used by the request
 constexpr int kTraceSlot = 7;        // trace(G C G^T) when computed
-// Persistent batched grids: 8 resident waves on each of the 1024 SIMDs.
-constexpr unsigned kPersistentBlocks = 8 * 1024 / (kBlock / 64);
+// Largest grid of one batched launch (a larger batch is split over launches).
+constexpr int64_t kMaxGridBlocks = int64_t(1) << 30;
 
 struct FwdJob {
     const double *xn, *yn, *zn, *ox, *oy, *oz, *w2;
@@ -68,6 +70,16 @@ struct AdjJob {
     int32_t ny1, nz, nparts, nkc;
 };
 
+// Pointers read from a job table are generic pointers to the compiler, so
+// loads through them would go through the flat path in vector registers.
+// They all point to device global memory: casting through the global address
+// space lets the compiler use global (and, for wave-uniform addresses, scalar)
+// loads, as it does for the kernel arguments of the single-call kernels.
+template <typename T>
+__device__ __forceinline__ T *global_ptr(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 template <typename Job>
 __device__ __forceinline__ int find_job(const Job *__restrict__ jobs, int njobs, int64_t vb) {
     int lo = 0, hi = njobs - 1;
@@ -78,28 +90,32 @@ __device__ __forceinline__ int find_job(const Job *__restrict__ jobs, int njobs,
     return lo;
 }
 
+// One block per virtual block of the batch: the block finds its request in the
+// job table and runs the same per-block body as the single-call kernel.
 __global__ __launch_bounds__(kBlock) void k_forward_batched(const FwdJob *__restrict__ jobs, int njobs,
-                                                            int64_t total) {
-    for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        const FwdJob &j = jobs[find_job(jobs, njobs, vb)];
-        const int64_t local = vb - j.block_begin;
-        forward_mixed_block(j.xn, j.yn, j.zn, j.ny1, j.nz, j.hk, j.ox, j.oy, j.oz, j.n, j.w2, j.ncols,
-                            j.cols_per_chunk, (int)(local % j.nchunk), local / j.nchunk, j.partial);
-    }
+                                                            int64_t base) {
+    const int64_t vb = base + blockIdx.x;
+    const FwdJob &j = jobs[find_job(jobs, njobs, vb)];
+    const int64_t local = vb - j.block_begin;
+    forward_mixed_block(global_ptr(j.xn), global_ptr(j.yn), global_ptr(j.zn), j.ny1, j.nz,
+                        global_ptr(j.hk), global_ptr(j.ox), global_ptr(j.oy), global_ptr(j.oz), j.n,
+                        global_ptr(j.w2), j.ncols, j.cols_per_chunk, (int)(local % j.nchunk),
+                        local / j.nchunk, global_ptr(j.partial));
 }
 
 __global__ __launch_bounds__(kBlock) void k_adjoint_batched(const AdjJob *__restrict__ jobs, int njobs,
-                                                            int64_t total) {
-    for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        const AdjJob &j = jobs[find_job(jobs, njobs, vb)];
-        int64_t local = vb - j.block_begin;
-        const int part = (int)(local % j.nparts);
-        local /= j.nparts;
-        const int kc = (int)(local % j.nkc);
-        local /= j.nkc;
-        adjoint_mixed_block(j.xn, j.yn, j.zn, j.ny1, j.nz, j.hk, j.ox, j.oy, j.oz, j.v, j.n,
-                            j.obs_per_part, j.ncols, j.nkc, part, kc, local, j.upart);
-    }
+                                                            int64_t base) {
+    const int64_t vb = base + blockIdx.x;
+    const AdjJob &j = jobs[find_job(jobs, njobs, vb)];
+    int64_t local = vb - j.block_begin;
+    const int part = (int)(local % j.nparts);
+    local /= j.nparts;
+    const int kc = (int)(local % j.nkc);
+    local /= j.nkc;
+    adjoint_mixed_block(global_ptr(j.xn), global_ptr(j.yn), global_ptr(j.zn), j.ny1, j.nz,
+                        global_ptr(j.hk), global_ptr(j.ox), global_ptr(j.oy), global_ptr(j.oz),
+                        global_ptr(j.v), j.n, j.obs_per_part, j.ncols, j.nkc, part, kc, local,
+                        global_ptr(j.upart));
 }
 
 // scal[kLambdaSlot] = lambda >= 0 ? lambda : 1e-2 * scal[kTraceSlot] / n
@@ -303,9 +319,11 @@ int grav_server::step(std::vector<Request *> &reqs) {
     }
     if (na) {
         STEP_TRY(hipMemcpyAsync(ajobs_dev, ajobs_host, na * sizeof(AdjJob), hipMemcpyHostToDevice, st));
-        const unsigned grid = (unsigned)std::min<int64_t>(atotal, kPersistentBlocks);
-        k_adjoint_batched<<<grid, kBlock, 0, st>>>(ajobs_dev, na, atotal);
-        STEP_TRY(hipGetLastError());
+        for (int64_t base = 0; base < atotal; base += kMaxGridBlocks) {
+            const unsigned grid = (unsigned)std::min<int64_t>(atotal - base, kMaxGridBlocks);
+            k_adjoint_batched<<<grid, kBlock, 0, st>>>(ajobs_dev, na, base);
+            STEP_TRY(hipGetLastError());
+        }
     }
     for (Request *q : reqs) {
         if (q->phase != Phase::CG && q->phase != Phase::Final) continue;
@@ -331,9 +349,11 @@ int grav_server::step(std::vector<Request *> &reqs) {
     }
     if (nf) {
         STEP_TRY(hipMemcpyAsync(fjobs_dev, fjobs_host, nf * sizeof(FwdJob), hipMemcpyHostToDevice, st));
-        const unsigned grid = (unsigned)std::min<int64_t>(ftotal, kPersistentBlocks);
-        k_forward_batched<<<grid, kBlock, 0, st>>>(fjobs_dev, nf, ftotal);
-        STEP_TRY(hipGetLastError());
+        for (int64_t base = 0; base < ftotal; base += kMaxGridBlocks) {
+            const unsigned grid = (unsigned)std::min<int64_t>(ftotal - base, kMaxGridBlocks);
+            k_forward_batched<<<grid, kBlock, 0, st>>>(fjobs_dev, nf, base);
+            STEP_TRY(hipGetLastError());
+        }
     }
     for (Request *q : reqs) {
         const int64_t n = q->o.n;
