@@ -36,17 +36,18 @@ import workloads  # noqa: E402
 # per second (FMA = one operation).  Algorithmic cost of one (observation,
 # vertical edge segment) pair: the minimal gfx950 instruction sequence of the
 # edge-segment formula (per-operation table in the design notes), 94
-# instructions for layers near the top and 84 for "deep" layers (top at least
-# 9 thicknesses below the mesh top, where the atan difference needs no range
-# reduction).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log) and 2 are
+# instructions for layers near the top and 78 for "deep" layers (top at least
+# 9 thicknesses and 1 mm below the mesh top, where the atan difference needs no
+# range reduction and no limit select is needed).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log) and 2 are
 # FP64.  Issue cost relative to an FP32 add, measured with --issue-probe
 # (dependent chains of one instruction class): a transcendental takes 2 slots,
 # an FP64 FMA 1; issue slots per pair = instructions + 6 * (2 - 1).
 PEAK_SLOTS = 157.3e12 / 2.0
-INSTR_SHALLOW, INSTR_DEEP = 94, 84
+INSTR_SHALLOW, INSTR_DEEP = 94, 78
 N_TRANS, N_FP64 = 6, 2
 TRANS_COST, FP64_COST = 2, 1
 DEEP_RATIO = 9.0
+DEEP_MIN_DEPTH = 1e-3
 
 
 def slots_per_pair(instr: int) -> int:
@@ -55,9 +56,10 @@ def slots_per_pair(instr: int) -> int:
 
 def first_deep_layer(zn) -> int:
     """Same rule as the library: every layer from this index on has its top at
-    least DEEP_RATIO thicknesses below the mesh top."""
+    least DEEP_RATIO thicknesses and DEEP_MIN_DEPTH below the mesh top."""
     k = len(zn) - 1
-    while k > 0 and (zn[k - 1] - zn[0]) >= DEEP_RATIO * (zn[k] - zn[k - 1]):
+    while (k > 0 and (zn[k - 1] - zn[0]) >= DEEP_RATIO * (zn[k] - zn[k - 1])
+           and (zn[k - 1] - zn[0]) >= DEEP_MIN_DEPTH):
         k -= 1
     return k
 

@@ -111,6 +111,7 @@ __device__ __forceinline__ float log1p_pos(float t) {
 
 constexpr float kTinyOffset = 1.0e-4f;   // metres
 constexpr double kDeepRatio = 9.0;       // layer top >= 9 h below the mesh top => "deep"
+constexpr double kDeepMinDepth = 1e-3;   // ... and >= 1 mm below it (metres)
 
 // Per (observation, mesh column) quantities, FP32, from FP64 differences.
 struct Column {
@@ -169,7 +170,10 @@ __device__ __forceinline__ Node make_node(const Column &c, float z) {
 // S = Psi(x, y, z2) - Psi(x, y, z1) for one vertical edge segment between
 // node t (top, depth z1 >= 0) and node b (bottom, z2 = z1 + h).
 //
-// kDeep: the segment's layer starts at least 9 h below the mesh top.  Since
+// kDeep: the segment's layer starts at least 9 h (and at least 1 mm) below the
+// mesh top.  Then z1 > 0, so x^2 + z1^2, y^2 + z1^2, R1 + |y|, R1 + |x| and
+// the atan-difference denominator are all positive for every observation and
+// the limit selects of the general path are not needed.  Since
 // z1 >= (layer top - mesh top) for every observation on or above the top, and
 // the atan-difference argument obeys |delta| <= h (z1 + h) / z1^2 (bound from
 // z1 R1 + z2 R2 >= (z1 + z2) R1, x^2 + y^2 + z1^2 + z2^2 <= 2 R2^2, AM-GM on the
@@ -185,8 +189,10 @@ __device__ __forceinline__ float edge_segment(const Column &c, const Node &t, co
     const float ry = t.R + fabsf(c.y), rx = t.R + fabsf(c.x);
     float denY = c.yneg ? (c.xx + t.zz) : ry;
     float denX = c.xneg ? (c.yy + t.zz) : rx;
-    denY = c.xnz ? denY : 1.0f;
-    denX = c.ynz ? denX : 1.0f;
+    if constexpr (!kDeep) {
+        denY = c.xnz ? denY : 1.0f;
+        denX = c.ynz ? denX : 1.0f;
+    }
     const float numY = c.yneg ? ry : 1.0f;
     const float numX = c.xneg ? rx : 1.0f;
     // dR/(R1 + y) and dR/(R1 + x) with dR = hz / (R1 + R2), one reciprocal
@@ -199,9 +205,17 @@ __device__ __forceinline__ float edge_segment(const Column &c, const Node &t, co
     const float den = (t.zR + b.zR) * fmaf(t.zR, b.zR, c.xy2);
     const float atd = kDeep ? fm::atan_small(num * fm::rcp(den)) : fm::atan_ratio(num, den);
     float S = h * at2;
-    S = (t.z > 0.0f) ? fmaf(t.z, atd, S) : S;
-    S = c.xnz ? fmaf(-c.x, lnY, S) : S;
-    S = c.ynz ? fmaf(-c.y, lnX, S) : S;
+    if constexpr (kDeep) {
+        // z1 > 0 keeps every denominator above zero, so every term is finite
+        // and the x = 0, y = 0 limits are the products themselves.
+        S = fmaf(t.z, atd, S);
+        S = fmaf(-c.x, lnY, S);
+        S = fmaf(-c.y, lnX, S);
+    } else {
+        S = (t.z > 0.0f) ? fmaf(t.z, atd, S) : S;
+        S = c.xnz ? fmaf(-c.x, lnY, S) : S;
+        S = c.ynz ? fmaf(-c.y, lnX, S) : S;
+    }
     return S;
 }
 

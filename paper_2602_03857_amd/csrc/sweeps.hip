@@ -45,7 +45,9 @@ __global__ void k_layer_thickness(const double *__restrict__ zn, int nz, float *
     }
     if (k == 0) {
         int kdeep = nz;
-        while (kdeep > 0 && (zn[kdeep - 1] - zn[0]) >= kDeepRatio * (zn[kdeep] - zn[kdeep - 1])) --kdeep;
+        while (kdeep > 0 && (zn[kdeep - 1] - zn[0]) >= kDeepRatio * (zn[kdeep] - zn[kdeep - 1]) &&
+               (zn[kdeep - 1] - zn[0]) >= kDeepMinDepth)
+            --kdeep;
         reinterpret_cast<int *>(hk + nz)[0] = kdeep;
     }
 }
