@@ -66,7 +66,8 @@ typedef enum {
     GRAV_EDEVICE = 3,   /* HIP runtime error; grav_last_error() has the text */
     GRAV_ENOCONV = 4,   /* positive warning: CG stopped at max_iter before reaching tol;
                            all outputs are valid */
-    GRAV_EBUSY = 5      /* server: request not finished yet / queue full */
+    GRAV_EBUSY = 5,     /* server: request not finished yet / queue full */
+    GRAV_ECANCELED = 6  /* server: the request was cancelled; its outputs are unspecified */
 } grav_status;
 
 typedef enum {
@@ -294,7 +295,8 @@ typedef struct {
 } grav_request;
 
 typedef struct {
-    int32_t status;          /* GRAV_OK, GRAV_ENOCONV (max_iter reached) or an error */
+    int32_t status;          /* GRAV_OK, GRAV_ENOCONV (max_iter reached), GRAV_ECANCELED
+                                or an error */
     int32_t iters;           /* CG iterations (inversions) */
     double relres;           /* final relative residual (inversions) */
     double lambda_used;      /* (inversions) */
@@ -321,6 +323,14 @@ int grav_server_poll(grav_server *srv, uint64_t ticket, int32_t *done, grav_requ
 /* Block until the request has finished; fills `info` (nullable), retires the
  * ticket, returns its status. */
 int grav_server_wait(grav_server *srv, uint64_t ticket, grav_request_info *info);
+
+/* Cancel a request.  A queued request is dropped at once; a request in
+ * flight stops after the scheduling step under way.  Either way it then
+ * reports done with status GRAV_ECANCELED (its outputs are unspecified) and
+ * is retired by grav_server_poll or grav_server_wait as usual.  A request
+ * that has already finished keeps its result.  Returns GRAV_OK, or
+ * GRAV_EINVAL for an unknown/retired ticket. */
+int grav_server_cancel(grav_server *srv, uint64_t ticket);
 
 /* Finish all admitted and queued requests, stop the worker, free the pool. */
 void grav_server_destroy(grav_server *srv);

@@ -13,7 +13,7 @@ import os
 
 from ._lib import (  # noqa: F401
     LIB_PATH, lib, GravError, GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV,
-    GRAV_EBUSY, GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU, GRAV_GAMMA,
+    GRAV_EBUSY, GRAV_ECANCELED, GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU, GRAV_GAMMA,
     OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND,
     CMesh, CObs, CtxOpts, CgOpts, CgInfo,
 )

@@ -6,7 +6,7 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrav.so")
 
-GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV, GRAV_EBUSY = range(6)
+GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV, GRAV_EBUSY, GRAV_ECANCELED = range(7)
 GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU = range(4)
 OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND = range(7)
 GRAV_GAMMA = 6.674e-11
@@ -100,6 +100,7 @@ def _load():
         "grav_server_submit": (ctypes.c_int, [vp, P(GravRequest), P(ctypes.c_uint64)]),
         "grav_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, P(i32), P(RequestInfo)]),
         "grav_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, P(RequestInfo)]),
+        "grav_server_cancel": (ctypes.c_int, [vp, ctypes.c_uint64]),
         "grav_server_destroy": (None, [vp]),
         "grav_set_timing": (ctypes.c_int, [vp, i32]),
         "grav_issue_rates": (ctypes.c_int, [vp, P(dbl), vp]),
@@ -121,5 +122,5 @@ EXPORTED = [
     "grav_trend_surface",
     "grav_invert", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
     "grav_reset_timing", "grav_issue_rates", "grav_server_create", "grav_server_submit", "grav_server_poll",
-    "grav_server_wait", "grav_server_destroy",
+    "grav_server_wait", "grav_server_cancel", "grav_server_destroy",
 ]

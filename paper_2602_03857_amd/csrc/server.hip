@@ -203,6 +203,7 @@ struct Request {
     int status = GRAV_OK;
     bool finished = false;   // worker-private: the last step completed it
     bool done = false;       // published under the server mutex after release
+    bool cancel = false;     // set under the server mutex by grav_server_cancel
     Clock::time_point t_submit, t_admit, t_done;
 };
 
@@ -444,6 +445,12 @@ void grav_server::run() {
         }
         std::vector<Request *> still;
         for (Request *q : active) {
+            if (q->cancel && !q->finished) {
+                q->finished = true;
+                q->phase = Phase::Done;
+                q->status = GRAV_ECANCELED;
+                q->t_done = Clock::now();
+            }
             if (q->finished) {
                 alloc->release(q->off, q->bytes);
                 (q->r.kind == GRAV_REQ_FORWARD ? free_fwd_slots : free_inv_slots).push_back(q->slot);
@@ -606,6 +613,28 @@ extern "C" int grav_server_wait(grav_server *s, uint64_t ticket, grav_request_in
     s->all.erase(ticket);
     delete q;
     return status;
+}
+
+extern "C" int grav_server_cancel(grav_server *s, uint64_t ticket) {
+    if (!s) return GRAV_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return GRAV_EINVAL;
+    Request *q = it->second;
+    if (q->done) return GRAV_OK;
+    auto qi = std::find(s->queue.begin(), s->queue.end(), q);
+    if (qi != s->queue.end()) {            // not admitted: nothing on the device
+        s->queue.erase(qi);
+        q->status = GRAV_ECANCELED;
+        q->phase = Phase::Done;
+        q->finished = true;
+        q->t_admit = q->t_done = Clock::now();
+        q->done = true;
+        s->cv_done.notify_all();
+    } else {
+        q->cancel = true;                  // the worker stops it after the current step
+    }
+    return GRAV_OK;
 }
 
 extern "C" void grav_server_destroy(grav_server *s) {

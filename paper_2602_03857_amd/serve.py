@@ -8,7 +8,7 @@ import threading
 import torch
 
 from ._lib import (lib, GravError, GravRequest, RequestInfo, ServerOpts, CgOpts, GRAV_OK,
-                   GRAV_ENOCONV)
+                   GRAV_ENOCONV, GRAV_ECANCELED)
 from .api import DeviceMesh, DeviceObs, _check
 
 REQ_FORWARD, REQ_INVERT = 0, 1
@@ -94,6 +94,13 @@ class Server:
         rc = lib.grav_server_wait(self._h, ticket, ctypes.byref(ri))
         with self._lock:
             self._keep.pop(ticket, None)
-        if rc not in (GRAV_OK, GRAV_ENOCONV):
+        if rc not in (GRAV_OK, GRAV_ENOCONV, GRAV_ECANCELED):
             raise GravError(rc, f"request {ticket} failed")
         return _info(ri)
+
+    def cancel(self, ticket: int) -> None:
+        """Cancel a queued or running request; it then reports status
+        GRAV_ECANCELED through poll / wait (outputs unspecified)."""
+        rc = lib.grav_server_cancel(self._h, ticket)
+        if rc != GRAV_OK:
+            raise GravError(rc, f"unknown ticket {ticket}")

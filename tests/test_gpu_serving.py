@@ -1,6 +1,8 @@
 """GPU tests of the continuous-batching server: a request's result is the
 same (bitwise) alone and in a mix, equals the single-call operators, memory
 admission queues instead of failing, and bad requests are rejected."""
+import time
+
 import numpy as np
 import pytest
 
@@ -197,3 +199,35 @@ def test_serving_stream_largest_requests_sampled():
     assert info_f["status"] == 0 and err <= 1e-5
     assert all(i["status"] in (0, 4) for i in infos)
     assert all(np.all(np.isfinite(to_np(it[3]))) for it in items)
+
+
+def test_cancel_queued_and_running_requests(g):
+    """Cancelling a queued inversion drops it at once; cancelling a running one
+    stops it after the current step; both report GRAV_ECANCELED, and the
+    server keeps serving (a later request equals the single-call result)."""
+    import torch
+    cases = _requests()
+    (ka, pa), (kb, pb) = cases[0], cases[2]
+    ctx = g.Context(0)
+    with g.Server(0, max_active=1, budget_bytes=1 << 30) as srv:
+        da, db = _device_problem(g, ka, pa), _device_problem(g, kb, pb)
+        ta = srv.submit_invert(da["mesh"], da["obs"], da["d_obs"], da["w"], da["m_out"],
+                               lam=-1.0, fixed_iters=1_000_000)  # runs until cancelled
+        tb = _submit(srv, kb, db)                                # waits for the one slot
+        srv.cancel(tb)
+        ib = srv.wait(tb)
+        assert ib["status"] == g.GRAV_ECANCELED and ib["run_ms"] == 0.0
+        time.sleep(0.3)                                          # let A run some steps
+        srv.cancel(ta)
+        ia = srv.wait(ta)
+        assert ia["status"] == g.GRAV_ECANCELED and 0 < ia["iters"] < 1_000_000
+        with pytest.raises(g.GravError):
+            srv.cancel(ta)                                       # retired ticket
+        dc = _device_problem(g, kb, pb)
+        ic = srv.wait(_submit(srv, kb, dc))
+        assert ic["status"] == 0
+    m, _, inf = ctx.invert(dc["mesh"], dc["obs"], dc["d_obs"], dc["w"], lam=-1.0, tol=1e-8,
+                           max_iter=300, prec=g.GRAV_MIXED)
+    assert inf["iters"] == ic["iters"] and torch.equal(m, dc["m_out"])
+    ctx.close()
+    print(f"[serving] cancel: running request stopped after {ia['iters']} iterations", flush=True)
