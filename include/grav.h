@@ -192,6 +192,13 @@ typedef struct {
      * grav_invert only: the server requires history_cap = 0. */
     int32_t history_cap;
     double *history;
+    /* Warm start / resume: y0 (DEVICE, n doubles, or NULL = start from 0) is
+     * the initial data-space iterate; residuals stay relative to
+     * ||delta_d||.  y_out (DEVICE, n doubles, or NULL) receives the final
+     * iterate, so a solve stopped at max_iter can be resumed later with it as
+     * y0.  grav_invert only: the server requires both NULL. */
+    const double *y0;
+    double *y_out;
 } grav_cg_opts;
 
 typedef struct {

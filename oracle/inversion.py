@@ -74,19 +74,22 @@ def dataspace_apply(mesh, obs, wdepth, lam, v) -> np.ndarray:
     return prism.forward(mesh, obs, cov * prism.adjoint(mesh, obs, v)) + lam * np.asarray(v)
 
 
-def conjugate_gradient(apply, b, tol=0.0, max_iter=100, fixed_iters=None):
-    """Plain conjugate gradients on the SPD system A y = b from y0 = 0.
+def conjugate_gradient(apply, b, tol=0.0, max_iter=100, fixed_iters=None, y0=None):
+    """Plain conjugate gradients on the SPD system A y = b from y0 (default 0).
 
     Stops when ||b - A y|| / ||b|| <= tol (recursively updated residual) or
     after max_iter iterations; ``fixed_iters`` runs exactly that many.
-    Returns (y, iterations, relres_history)."""
+    Returns (y, iterations, relres_history), the history starting with the
+    relative residual of y0."""
     b = np.asarray(b, dtype=np.float64)
-    y = np.zeros_like(b)
-    r = b.copy()
+    y = np.zeros_like(b) if y0 is None else np.array(y0, dtype=np.float64)
+    r = b.copy() if y0 is None else b - apply(y)
     p = r.copy()
     rr = float(r @ r)
-    bnorm = np.sqrt(rr)
-    hist = [1.0]
+    bnorm = np.linalg.norm(b)
+    hist = [np.sqrt(rr) / bnorm]
+    if fixed_iters is None and hist[0] <= tol:
+        return y, 0, hist
     n_iter = fixed_iters if fixed_iters is not None else max_iter
     it = 0
     for it in range(1, n_iter + 1):
@@ -117,7 +120,7 @@ def invert_cg(mesh, obs, d_obs, wdepth, lam, m_ref=None, tol=1e-6, max_iter=200,
     return m, y, it, hist
 
 
-def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5, log=None):
+def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5, log=None, y0=None):
     """The paper's solver policy (Section 2.2: at most `outer` model updates,
     each at most `inner` CG iterations, stop at res <= tol, step-size
     backtracking), in the reading used here:
@@ -132,17 +135,21 @@ def restarted_cg(apply, b, inner=20, outer=30, tol=1e-4, max_halvings=5, log=Non
     * stop when ||r|| / ||b|| <= tol after a cycle, or after `outer` cycles.
 
     If ``log`` is a list, the recursive relative residual after every inner
-    iteration is appended to it (the misfit-versus-iteration record).
+    iteration is appended to it (the misfit-versus-iteration record).  ``y0``
+    starts from that iterate instead of 0 (residuals stay relative to ||b||).
 
     Returns (y, total_inner_iterations, outer_cycles, relres_history), the
     history holding the true relative residual after each cycle."""
     b = np.asarray(b, dtype=np.float64)
-    y = np.zeros_like(b)
+    y = np.zeros_like(b) if y0 is None else np.array(y0, dtype=np.float64)
     bnorm = np.linalg.norm(b)
-    hist = [1.0]
+    r = b - apply(y)
+    hist = [float(np.linalg.norm(r)) / bnorm]
     total = 0
-    q_old = 0.0
+    q_old = -0.5 * float(y @ (b + r))     # Q(y0); 0 for y0 = 0
     cycles = 0
+    if hist[0] <= tol:
+        return y, 0, 0, hist
     for cycles in range(1, outer + 1):
         y_old = y.copy()
         r = b - apply(y)

@@ -34,7 +34,8 @@ class CgOpts(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("max_halvings", ctypes.c_int32), ("history_cap", ctypes.c_int32),
-                ("history", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("y0", ctypes.c_void_p),
+                ("y_out", ctypes.c_void_p)]
 
 
 class CgInfo(ctypes.Structure):

@@ -219,14 +219,16 @@ class Context:
     def invert(self, mesh, obs, d_obs, wdepth, lam=-1.0, m_ref=None, tol=1e-6, max_iter=200,
                fixed_iters=0, m_out=None, d_pred=None, want_pred=False, prec=GRAV_MIXED,
                stream=None, precond=0, restart=0, max_cycles=30, max_halvings=5,
-               history_cap=0):
+               history_cap=0, y0=None, y_out=None):
         """Data-space CG inversion (Eq. 11).  Returns (m, d_pred or None, info dict).
 
         restart > 0 selects the restarted policy (cycles of at most `restart`
         CG iterations, at most `max_cycles` cycles, step backtracking with at
         most `max_halvings` halvings per cycle); max_iter is then unused.
         history_cap > 0 returns the misfit log (relative residual after each
-        CG iteration, at most history_cap entries) as info["history"]."""
+        CG iteration, at most history_cap entries) as info["history"].
+        y0 (n,) starts CG from that data-space iterate (warm start / resume);
+        y_out (n,) receives the final iterate."""
         _check(d_obs, torch.float64, obs.n, "d_obs", self.device)
         _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
         if m_ref is not None:
@@ -238,10 +240,15 @@ class Context:
             d_pred = torch.empty(obs.n, dtype=torch.float64, device=self.device)
         if d_pred is not None:
             _check(d_pred, torch.float64, obs.n, "d_pred", self.device)
+        for t, name in ((y0, "y0"), (y_out, "y_out")):
+            if t is not None:
+                _check(t, torch.float64, obs.n, name, self.device)
         hist = (ctypes.c_double * max(int(history_cap), 1))()
         cg = CgOpts(float(tol), int(max_iter), int(fixed_iters), int(precond), int(restart),
                     int(max_cycles), int(max_halvings), int(history_cap),
-                    ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history_cap > 0 else None)
+                    ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history_cap > 0 else None,
+                    y0.data_ptr() if y0 is not None else None,
+                    y_out.data_ptr() if y_out is not None else None)
         info = CgInfo()
         rc = lib.grav_invert(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c), d_obs.data_ptr(),
                              wdepth.data_ptr(), float(lam),

@@ -405,7 +405,7 @@ extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     rc = validate_on_device(ctx, g, o, st,
                             {ArrayCheck{wdepth, g.ncells(), true}, ArrayCheck{d_obs, o.n, false},
-                             ArrayCheck{m_ref, g.ncells(), false}});
+                             ArrayCheck{m_ref, g.ncells(), false}, ArrayCheck{cg->y0, o.n, false}});
     if (rc) return rc;
     return grav::run_invert(ctx, g, o, d_obs, wdepth, lambda, m_ref, *cg, m_out, d_pred, info, prec, st);
 }

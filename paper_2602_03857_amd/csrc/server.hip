@@ -555,7 +555,8 @@ extern "C" int grav_server_submit(grav_server *s, const grav_request *req, uint6
                 const grav_cg_opts &cg = req->cg;
                 if (!req->d_obs || !req->wdepth || !req->m_out || !std::isfinite(req->lambda) ||
                     (cg.fixed_iters <= 0 && (cg.max_iter < 1 || !(cg.tol >= 0.0))) ||
-                    cg.precond != 0 || cg.restart != 0 || cg.history_cap != 0)
+                    cg.precond != 0 || cg.restart != 0 || cg.history_cap != 0 || cg.y0 ||
+                    cg.y_out)
                     rc = GRAV_EINVAL;
                 else
                     rc = validate_on_device(v, g, o, s->vstream,

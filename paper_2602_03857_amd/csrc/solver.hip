@@ -23,8 +23,9 @@ static int read_scalars(grav_ctx *ctx, hipStream_t st) {
     return GRAV_OK;
 }
 
-// Restarted CG (the solver policy of Section 2.2).  On entry y = 0, r holds
-// delta_d (= dd) and scal[kRR], scal[kB2] hold its squared norm.  Each cycle
+// Restarted CG (the solver policy of Section 2.2).  On entry y holds the
+// initial iterate (0 or a warm start), r = dd - A y its residual and scal[kB2]
+// the squared norm of dd (= delta_d).  Each cycle
 // restarts from the true residual; after a cycle the true residual r = dd - A y
 // is formed and, while Q(y) = -(y . (dd + r)) / 2 rose above the previous
 // cycle's value, the step is halved.  The residual is affine in y, so the
@@ -48,7 +49,7 @@ static int restarted_cg(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, c
     s.relres = b2 > 0.0 ? 1.0 : 0.0;
     s.converged = b2 == 0.0;
     double rr = b2;         // r . r of the current (true) residual
-    double q_prev = 0.0;    // Q(0) = 0
+    double q_prev = 0.0;    // Q of the iterate the cycle starts from
     // Q(y) and r.r of the current y, r
     auto objective = [&](double *q_val) -> int {
         HIP_TRY(launch_lincomb(q, 1.0, dd, 1.0, r, n, st), "lincomb");
@@ -62,6 +63,12 @@ static int restarted_cg(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, c
         rr = ctx->h_scal[kRR];
         return GRAV_OK;
     };
+    if (!s.converged) {
+        int rc = objective(&q_prev);            // Q(0) = 0 and r.r = b2 without a warm start
+        if (rc) return rc;
+        s.relres = std::sqrt(rr / b2);
+        s.converged = s.relres <= cg.tol;
+    }
     while (s.cycles < cg.max_cycles && !s.converged) {
         ++s.cycles;
         HIP_TRY(launch_sub(y, nullptr, yold, n, st), "copy");
@@ -131,34 +138,48 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
         if (lambda < 0.0) lambda = 1e-2 * trace / (double)n;
     }
 
-    // r = delta_d = d_obs - G m_ref ; p = r (or M^-1 r) ; y = 0
+    // r = delta_d = d_obs - G m_ref ; ||delta_d||^2 -> scal[kB2] (and kRR)
     if (m_ref) {
         int rc = op_forward(ctx, ar, g, o, m_ref, r, prec, st, -GRAV_GAMMA, d_obs, 1.0);
         if (rc) return rc;
     } else {
         HIP_TRY(launch_sub(d_obs, nullptr, r, n, st), "copy");
     }
-    HIP_TRY(launch_fill(y, 0.0, n, st), "fill");
+    HIP_TRY(launch_dot(r, r, n, dpart, st), "dot");
+    HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+    if (restarted) HIP_TRY(launch_sub(r, nullptr, dd, n, st), "copy");
+    // y = y0 (warm start: r = delta_d - A y0) or 0
+    if (cg.y0) {
+        HIP_TRY(launch_sub(cg.y0, nullptr, y, n, st), "copy");
+        int rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, y, q, prec, st);
+        if (rc) return rc;
+        HIP_TRY(launch_lincomb(r, 1.0, r, -1.0, q, n, st), "residual");
+    } else {
+        HIP_TRY(launch_fill(y, 0.0, n, st), "fill");
+    }
+    // p = r (or M^-1 r); r.r (and r.z) of the starting residual
     if (pc) {
         HIP_TRY(launch_pcg_setup(dinv, lambda, dinv, r, z, p, n, dpart, dpart2, st), "pcg setup");
-        HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+        HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kRR, st), "dot");
         HIP_TRY(launch_dot_finish(dpart2, scal, kFinishPlain, kRZ, st), "dot");
     } else {
         HIP_TRY(launch_sub(r, nullptr, p, n, st), "copy");
-        HIP_TRY(launch_dot(r, r, n, dpart, st), "dot");
-        HIP_TRY(launch_dot_finish(dpart, scal, kFinishInit, 0, st), "dot");
+        if (cg.y0) {
+            HIP_TRY(launch_dot(r, r, n, dpart, st), "dot");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kRR, st), "dot");
+        }
     }
     int rc = read_scalars(ctx, st);
     if (rc) return rc;
     const double b2 = ctx->h_scal[kB2];
+    if (b2 == 0.0 && cg.y0) HIP_TRY(launch_fill(y, 0.0, n, st), "fill");   // delta_d = 0: y = 0
 
     const bool fixed = !restarted && cg.fixed_iters > 0;
     const int iters_cap = restarted ? 0 : fixed ? cg.fixed_iters : cg.max_iter;
     int it = 0, cycles = 1, halvings = 0;
-    double relres = b2 > 0.0 ? 1.0 : 0.0;
-    bool converged = b2 == 0.0;
+    double relres = b2 > 0.0 ? std::sqrt(ctx->h_scal[kRR] / b2) : 0.0;
+    bool converged = b2 == 0.0 || (!fixed && relres <= cg.tol);
     if (restarted) {
-        HIP_TRY(launch_sub(r, nullptr, dd, n, st), "copy");
         SolveStats ss;
         rc = restarted_cg(ctx, ar, g, o, wdepth, lambda, prec, st, cg, dd, y, r, p, q, yold, rold,
                           b2, &ss);
@@ -199,6 +220,7 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
         relres = std::sqrt(ctx->h_scal[kRR] / b2);
     }
 
+    if (cg.y_out) HIP_TRY(launch_sub(y, nullptr, cg.y_out, n, st), "copy");
     // m = m_ref + C G^T y ; optional predicted data
     rc = op_adjoint(ctx, ar, g, o, y, m_out, prec, st, GRAV_GAMMA, wdepth, m_ref);
     if (rc) return rc;

@@ -73,7 +73,7 @@ class Server:
         _check(m_out, torch.float64, mesh.ncells, "m_out", self.device)
         req = GravRequest(kind=REQ_INVERT, mesh=mesh.c, obs=obs.c, d_obs=d_obs.data_ptr(),
                           wdepth=wdepth.data_ptr(), lam=float(lam),
-                          cg=CgOpts(float(tol), int(max_iter), int(fixed_iters), 0, 0, 0, 0, 0, None),
+                          cg=CgOpts(float(tol), int(max_iter), int(fixed_iters), 0, 0, 0, 0, 0, None, None, None),
                           m_out=m_out.data_ptr())
         return self._submit(req, (mesh, obs, d_obs, wdepth, m_out))
 

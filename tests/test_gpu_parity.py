@@ -293,6 +293,39 @@ def test_invert_misfit_history_plain_cg(g, ctx, config1_ref):
     assert len(h) == full["iters"] and h[-1] == full["relres"] <= 1e-6 < min(h[:-1])
 
 
+def test_invert_warm_start_and_resume(g, ctx, config1_ref):
+    """Warm start / resume: CG from an oracle iterate (10 oracle iterations)
+    follows the oracle's resumed history and returns its final iterate in
+    y_out; from the Cholesky solution no iteration is needed; the restarted
+    policy resumes the same way."""
+    import torch
+    p, G, d_obs, trace, lam, m_chol = config1_ref
+    mesh, obs = _dev(g, p)
+    cov = inversion.covariance_from_weights(p.wdepth)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    y10, _, _ = inversion.conjugate_gradient(lambda v: A @ v, d_obs, fixed_iters=10)
+    _, it_ref, hist_ref = inversion.conjugate_gradient(lambda v: A @ v, d_obs, tol=1e-6,
+                                                       max_iter=500, y0=y10)
+    y_out = torch.empty(p.obs.n, dtype=torch.float64, device="cuda")
+    m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-6, max_iter=500,
+                            prec=g.GRAV_FP64, y0=_t(y10), y_out=y_out, history_cap=1000)
+    print(f"[parity] resumed CG: {info['iters']} iterations (oracle {it_ref})", flush=True)
+    assert info["converged"] and abs(info["iters"] - it_ref) <= max(3, it_ref // 10)
+    np.testing.assert_allclose(info["history"][:_EARLY], hist_ref[1:1 + _EARLY], rtol=1e-6)
+    yo = to_np(y_out)
+    assert np.linalg.norm(d_obs - A @ yo) <= 2e-6 * np.linalg.norm(d_obs)
+    assert rel_l2(to_np(m), cov * (G.T @ yo)) <= 1e-9
+    y_ch = np.linalg.solve(A, d_obs)
+    m2, _, info2 = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-6,
+                              prec=g.GRAV_FP64, y0=_t(y_ch))
+    assert info2["iters"] == 0 and info2["converged"] and rel_l2(to_np(m2), m_chol) <= 1e-8
+    y_r, _, cyc, _ = inversion.restarted_cg(lambda v: A @ v, d_obs, 20, 30, 1e-6, y0=y10)
+    m3, _, info3 = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, tol=1e-6, restart=20,
+                              max_cycles=30, prec=g.GRAV_FP64, y0=_t(y10))
+    assert info3["converged"] and abs(info3["cycles"] - cyc) <= 1
+    assert rel_l2(to_np(m3), cov * (G.T @ y_r)) <= 2e-5
+
+
 def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
     p, G, d_obs, trace, lam, m_chol = config1_ref
     mesh, obs = _dev(g, p)

@@ -460,3 +460,24 @@ def test_trend_surface_plane_on_symmetric_grid_closed_form():
     t, _ = trend.trend_surface(1e3 * u + 4e5, 1e3 * w + 7e6, v, 1)
     closed = v.mean() + u * (u @ v) / (u @ u) + w * (w @ v) / (w @ w)
     np.testing.assert_allclose(t, closed, atol=1e-12 * np.abs(v).max())
+
+
+def test_cg_warm_start_resumes_the_solve():
+    """Warm start: starting from the exact solution stops at once; resuming a
+    stopped solve from its iterate reaches the Cholesky solution; the history
+    starts at the relative residual of the starting iterate."""
+    p, G, cov, d_obs, lam = _tiny_problem(9)
+    A = inversion.dataspace_matrix(G, cov, lam)
+    y_chol = np.linalg.solve(A, d_obs)
+    y, it, hist = inversion.conjugate_gradient(lambda v: A @ v, d_obs, tol=1e-10, y0=y_chol)
+    assert it == 0 and hist[0] <= 1e-10
+    y4, _, _ = inversion.conjugate_gradient(lambda v: A @ v, d_obs, fixed_iters=4)
+    y_res, it_res, h_res = inversion.conjugate_gradient(lambda v: A @ v, d_obs, tol=1e-12,
+                                                        max_iter=100, y0=y4)
+    assert np.isclose(h_res[0], np.linalg.norm(d_obs - A @ y4) / np.linalg.norm(d_obs), rtol=1e-12)
+    assert np.linalg.norm(y_res - y_chol) <= 1e-9 * np.linalg.norm(y_chol)
+    y_r, _, cycles, _ = inversion.restarted_cg(lambda v: A @ v, d_obs, inner=20, outer=30,
+                                               tol=1e-12, y0=y4)
+    assert np.linalg.norm(y_r - y_chol) <= 1e-9 * np.linalg.norm(y_chol)
+    _, tot0, cyc0, _ = inversion.restarted_cg(lambda v: A @ v, d_obs, tol=1e-8, y0=y_chol)
+    assert tot0 == 0 and cyc0 == 0
