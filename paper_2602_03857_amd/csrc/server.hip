@@ -25,6 +25,7 @@
 // it is batched with, and the hardware dispatcher balances blocks of uneven
 // cost across the GPU.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -433,7 +434,9 @@ void grav_server::run() {
         if (active.empty()) continue;   // head of queue cannot fit: nothing else can run
         std::vector<Request *> work = active;
         lk.unlock();
+        roctxRangePushA("grav server step");
         const int err = step(work);
+        roctxRangePop();
         lk.lock();
         if (err) {
             for (Request *q : work) {

@@ -4,11 +4,21 @@
 // device.  Also the workspace sizing shared by every entry point.
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <cmath>
 
 #include "api_internal.h"
 
 namespace grav {
+
+// A named range (rocprofv3 --marker-trace) for the lifetime of the object.
+struct RoctxRange {
+    explicit RoctxRange(const char *name) { roctxRangePushA(name); }
+    ~RoctxRange() { roctxRangePop(); }
+    RoctxRange(const RoctxRange &) = delete;
+    RoctxRange &operator=(const RoctxRange &) = delete;
+};
 
 #define HIP_TRY(expr, where)                                       \
     do {                                                           \
@@ -75,6 +85,7 @@ static int restarted_cg(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, c
         HIP_TRY(launch_sub(r, nullptr, rold, n, st), "copy");
         HIP_TRY(launch_sub(r, nullptr, p, n, st), "copy");
         for (int j = 0; j < cg.restart && std::sqrt(rr / b2) > cg.tol; ++j) {
+            const RoctxRange range("grav cg iteration");
             int rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
             if (rc) return rc;
             HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
@@ -191,6 +202,7 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
         converged = ss.converged;
     }
     for (it = restarted ? it : 0; it < iters_cap && !converged;) {
+        const RoctxRange range("grav cg iteration");
         rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
         if (rc) return rc;
         HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
