@@ -222,6 +222,16 @@ def run_serve(args) -> int:
                                                if it["kind"] == "forward") / wall,
            "mean_cg_iters": float(np.mean(list(iters.values()))) if iters else 0}
 
+    # error of every served forward result against the plain FP64 path
+    errs = []
+    for it in items:
+        if it["kind"] == "forward":
+            ref = ctx.forward(it["mesh"], it["obs"], it["m"], prec=g.GRAV_FP64)
+            errs.append(float(torch.linalg.norm(it["d"] - ref) / torch.linalg.norm(ref)))
+    if errs:
+        res["forward_rel_l2_vs_fp64"] = {"requests": len(errs), "max": max(errs),
+                                         "median": float(np.median(errs))}
+
     # one-at-a-time FIFO of the plain FP64 path on the same arrivals
     nb = min(args.serve_baseline_requests, len(items))
     if nb > 0:
