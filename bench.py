@@ -136,6 +136,43 @@ def multi_model_extras(g, torch, dev):
     return res
 
 
+def config2_extras(g, torch, dev):
+    """The 10,000-observation x 500,000-prism forward/adjoint workload in both
+    precisions: kernel times and errors on the stored FP64 oracle rows/cells."""
+    p = workloads.config2()
+    mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
+    obs = g.DeviceObs.from_survey(p.obs, dev)
+    m = torch.as_tensor(p.m, device=dev)
+    v = torch.as_tensor(p.probe_v, device=dev)
+    gold_path = os.path.join(ROOT, "tests", "golden", "config2_rows.npz")
+    gold = np.load(gold_path) if os.path.exists(gold_path) else None
+    ctx = g.Context(0, validate=False)
+    ctx.set_timing(True)
+    res = {}
+    for prec, tag in ((g.GRAV_MIXED, "mixed"), (g.GRAV_FP64, "f64")):
+        d = ctx.forward(mesh, obs, m, prec=prec)
+        gt = ctx.adjoint(mesh, obs, v, prec=prec)
+        torch.cuda.synchronize()
+        ctx.reset_timing()
+        for _ in range(3):
+            ctx.forward(mesh, obs, m, d, prec=prec)
+            ctx.adjoint(mesh, obs, v, gt, prec=prec)
+        torch.cuda.synchronize()
+        fms, fn = ctx.kernel_time("forward_" + tag)
+        ams, an = ctx.kernel_time("adjoint_" + tag)
+        res[f"config2_forward_{tag}_kernel_ms"] = fms / fn
+        res[f"config2_adjoint_{tag}_kernel_ms"] = ams / an
+        if gold is not None:
+            dn = d.cpu().numpy()[gold["rows"]]
+            res[f"config2_forward_{tag}_rel_l2"] = float(
+                np.linalg.norm(dn - gold["d"]) / np.linalg.norm(gold["d"]))
+            gn = gt.cpu().numpy()[gold["cells"]]
+            res[f"config2_adjoint_{tag}_rel_l2"] = float(
+                np.linalg.norm(gn - gold["gtv"]) / np.linalg.norm(gold["gtv"]))
+    ctx.close()
+    return res
+
+
 def _serve_inputs(g, torch, dev, reqs, ctx):
     """Materialise the request stream on the device (not timed): meshes,
     surveys, models; noisy data for inversions (d_clean from the library)."""
@@ -498,6 +535,8 @@ def main() -> int:
 
     if not args.no_extras and not args.no_multi:
         extras.update(multi_model_extras(g, torch, dev))
+    if not args.no_extras:
+        extras.update(config2_extras(g, torch, dev))
 
     out = {
         "metric": "prism-obs pairs/s for G.m at 3.3M x 178,797",
