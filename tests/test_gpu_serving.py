@@ -231,3 +231,36 @@ def test_cancel_queued_and_running_requests(g):
     assert inf["iters"] == ic["iters"] and torch.equal(m, dc["m_out"])
     ctx.close()
     print(f"[serving] cancel: running request stopped after {ia['iters']} iterations", flush=True)
+
+
+def test_concurrent_submission_from_threads(g):
+    """Requests submitted from several threads at once are all served, each
+    bitwise equal to its single-call result."""
+    import threading
+    import torch
+    ctx = g.Context(0)
+    cases = [workloads.random_case(300 + i, 9 + i, 7, 5, 90 + 13 * i, model="blocky")
+             for i in range(8)]
+    refs = [ctx.forward(g.DeviceMesh.from_mesh(p.mesh), g.DeviceObs.from_survey(p.obs), _t(p.m),
+                        prec=g.GRAV_MIXED) for p in cases]
+    outs = [torch.empty(p.obs.n, dtype=torch.float64, device="cuda") for p in cases]
+    errors = []
+    with g.Server(0, max_active=4, budget_bytes=1 << 30) as srv:
+        def client(idx):
+            try:
+                p = cases[idx]
+                mesh, obs = g.DeviceMesh.from_mesh(p.mesh), g.DeviceObs.from_survey(p.obs)
+                for _ in range(3):
+                    info = srv.wait(srv.submit_forward(mesh, obs, _t(p.m), outs[idx]))
+                    assert info["status"] == 0
+            except Exception as e:  # noqa: BLE001  (reported below)
+                errors.append(e)
+        threads = [threading.Thread(target=client, args=(i,)) for i in range(len(cases))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=120)
+    assert not errors, errors
+    for ref, out in zip(refs, outs):
+        assert torch.equal(ref, out)
+    ctx.close()
