@@ -49,7 +49,7 @@ __device__ __forceinline__ void forward_mixed_block(
         int k = 0;
         double w_a = w[0], w_b = w[nz > 1 ? 1 : 0];
         float h_a = hk[0], z_a = zrel[0], h_b = hk[nz > 1 ? 1 : 0], z_b = zrel[nz > 1 ? 1 : 0];
-#pragma unroll 8
+#pragma unroll 16
         for (; k < kdeep; ++k) {
             const int kn = k + 2 < nz ? k + 2 : nz - 1;
             const double wc = w_a;
@@ -61,7 +61,7 @@ __device__ __forceinline__ void forward_mixed_block(
             acc = fma(static_cast<double>(S), wc, acc);
             top = bot;
         }
-#pragma unroll 8
+#pragma unroll 16
         for (; k < nz; ++k) {
             const int kn = k + 2 < nz ? k + 2 : nz - 1;
             const double wc = w_a;
