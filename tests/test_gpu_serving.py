@@ -264,3 +264,22 @@ def test_concurrent_submission_from_threads(g):
     for ref, out in zip(refs, outs):
         assert torch.equal(ref, out)
     ctx.close()
+
+
+def test_largest_slot_count_with_many_small_requests(g):
+    """max_active at its cap (256): 300 small forward requests submitted at
+    once are all served; a sample is bitwise equal to the single-call path."""
+    import torch
+    p = workloads.random_case(400, 6, 5, 4, 70, model="blocky")
+    mesh, obs = g.DeviceMesh.from_mesh(p.mesh), g.DeviceObs.from_survey(p.obs)
+    m = _t(p.m)
+    with g.Context(0) as ctx:
+        ref = ctx.forward(mesh, obs, m, prec=g.GRAV_MIXED)
+    outs = [torch.empty(p.obs.n, dtype=torch.float64, device="cuda") for _ in range(300)]
+    with g.Server(0, max_active=256, budget_bytes=1 << 30) as srv:
+        tickets = [srv.submit_forward(mesh, obs, m, d) for d in outs]
+        infos = [srv.wait(t) for t in tickets]
+    assert all(i["status"] == 0 for i in infos)
+    assert all(torch.equal(d, ref) for d in outs[::37])
+    with pytest.raises(g.GravError):
+        g.Server(0, max_active=257)
