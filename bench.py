@@ -3,7 +3,7 @@
 
 Workload: 178,797 observations over a 150 x 150 x 147 prism mesh
 (3,307,500 prisms, 100 x 100 x 70 m cells), two dykes plus ten random
-bodies, synthetic and seeded (``workloads.config4``).  A step is one
+bodies, synthetic and seeded (``workloads.paper_scale``).  A step is one
 ``grav_forward`` call in GRAV_MIXED precision: coordinate differences, edge
 weights, the forward sweep and the partial-sum reduction, inputs already
 resident in HBM.  Metric: prism-observation pairs per second,
@@ -64,7 +64,7 @@ def first_deep_layer(zn) -> int:
     return k
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_mixed_config4_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_mixed_paper_scale_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_03857_amd", "csrc", f)
                   for f in ("sweeps.hip", "sweep_bodies.h", "edge_math.h", "grav_internal.h")]
 
@@ -78,7 +78,7 @@ def kernel_source_hash() -> str:
 
 
 def cpu_baseline(p, target_s: float, workers: int):
-    """FP64 oracle (as it stands) on a bounded sample of config-4 rows: batches
+    """FP64 oracle (as it stands) on a bounded sample of the paper-scale rows: batches
     of seeded rows until about target_s seconds of wall time."""
     from oracle import parallel
     rng = np.random.default_rng(777)
@@ -100,8 +100,8 @@ def cpu_baseline(p, target_s: float, workers: int):
 def multi_model_extras(g, torch, dev):
     """64 density models on the 500k-cell mesh with 10,000 observations:
     split-bf16 MFMA and FP32-VALU contractions against 64 single forwards."""
-    p3 = workloads.config2()
-    models = workloads.config3_models(p3.mesh).astype(np.float32)
+    p3 = workloads.ellipsoids_100x100x50()
+    models = workloads.smoothed_box_models(p3.mesh).astype(np.float32)
     mesh = g.DeviceMesh.from_mesh(p3.mesh, dev)
     obs = g.DeviceObs.from_survey(p3.obs, dev)
     mt = torch.as_tensor(models, device=dev)
@@ -136,15 +136,15 @@ def multi_model_extras(g, torch, dev):
     return res
 
 
-def config2_extras(g, torch, dev):
+def ellipsoids_extras(g, torch, dev):
     """The 10,000-observation x 500,000-prism forward/adjoint workload in both
     precisions: kernel times and errors on the stored FP64 oracle rows/cells."""
-    p = workloads.config2()
+    p = workloads.ellipsoids_100x100x50()
     mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
     obs = g.DeviceObs.from_survey(p.obs, dev)
     m = torch.as_tensor(p.m, device=dev)
     v = torch.as_tensor(p.probe_v, device=dev)
-    gold_path = os.path.join(ROOT, "tests", "golden", "config2_rows.npz")
+    gold_path = os.path.join(ROOT, "tests", "golden", "ellipsoids_100x100x50_rows.npz")
     gold = np.load(gold_path) if os.path.exists(gold_path) else None
     ctx = g.Context(0, validate=False)
     ctx.set_timing(True)
@@ -160,14 +160,14 @@ def config2_extras(g, torch, dev):
         torch.cuda.synchronize()
         fms, fn = ctx.kernel_time("forward_" + tag)
         ams, an = ctx.kernel_time("adjoint_" + tag)
-        res[f"config2_forward_{tag}_kernel_ms"] = fms / fn
-        res[f"config2_adjoint_{tag}_kernel_ms"] = ams / an
+        res[f"ellipsoids_forward_{tag}_kernel_ms"] = fms / fn
+        res[f"ellipsoids_adjoint_{tag}_kernel_ms"] = ams / an
         if gold is not None:
             dn = d.cpu().numpy()[gold["rows"]]
-            res[f"config2_forward_{tag}_rel_l2"] = float(
+            res[f"ellipsoids_forward_{tag}_rel_l2"] = float(
                 np.linalg.norm(dn - gold["d"]) / np.linalg.norm(gold["d"]))
             gn = gt.cpu().numpy()[gold["cells"]]
-            res[f"config2_adjoint_{tag}_rel_l2"] = float(
+            res[f"ellipsoids_adjoint_{tag}_rel_l2"] = float(
                 np.linalg.norm(gn - gold["gtv"]) / np.linalg.norm(gold["gtv"]))
     ctx.close()
     return res
@@ -209,7 +209,7 @@ def run_serve(args) -> int:
     import torch
     import paper_2602_03857_amd as g
     dev = torch.device("cuda", 0)
-    reqs = workloads.config5_stream()[: args.serve_requests]
+    reqs = workloads.serving_stream()[: args.serve_requests]
     ctx = g.Context(0, validate=False)
     items = _serve_inputs(g, torch, dev, reqs, ctx)
     pairs = [it["n"] * it["M"] for it in items]
@@ -310,7 +310,7 @@ def run_cg_full(args) -> int:
     below the 2 % noise); this mode times the solve, it checks no parity."""
     import torch
     import paper_2602_03857_amd as g
-    p = workloads.config4()
+    p = workloads.paper_scale()
     dev = torch.device("cuda", 0)
     mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
     obs = g.DeviceObs.from_survey(p.obs, dev)
@@ -342,7 +342,7 @@ def run_cg_full(args) -> int:
            "trace_s": 1e-3 * tr_ms, "forward_kernel_ms_avg": f_ms / max(f_n, 1),
            "adjoint_kernel_ms_avg": a_ms / max(a_n, 1), "relres": info["relres"],
            "lambda": info["lambda_used"], "data_misfit_rel": misfit, "noise_rel": noise,
-           "data": "synthetic (seeded config-4 survey, model and noise)"}
+           "data": "synthetic (seeded paper-scale survey, model and noise)"}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -410,7 +410,7 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
         return 0
 
-    p = workloads.config4()
+    p = workloads.paper_scale()
     n, M = p.obs.n, p.mesh.ncells
     pairs = n * M
 
@@ -486,7 +486,7 @@ def main() -> int:
 
     # error vs the oracle on the stored rows
     extras = {}
-    gold_path = os.path.join(ROOT, "tests", "golden", "config4_rows.npz")
+    gold_path = os.path.join(ROOT, "tests", "golden", "paper_scale_rows.npz")
     if os.path.exists(gold_path):
         gold = np.load(gold_path)
         dn = d.cpu().numpy()[gold["rows"]]
@@ -536,7 +536,7 @@ def main() -> int:
     if not args.no_extras and not args.no_multi:
         extras.update(multi_model_extras(g, torch, dev))
     if not args.no_extras:
-        extras.update(config2_extras(g, torch, dev))
+        extras.update(ellipsoids_extras(g, torch, dev))
 
     out = {
         "metric": "prism-obs pairs/s for G.m at 3.3M x 178,797",
@@ -550,8 +550,8 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
-        "data": "synthetic (seeded config-4 survey and model)",
-        "config": {"workload": "config4: G m, 178,797 obs x 3,307,500 prisms (150x150x147, "
+        "data": "synthetic (seeded paper-scale survey and model)",
+        "config": {"workload": "paper_scale: G m, 178,797 obs x 3,307,500 prisms (150x150x147, "
                                "100x100x70 m), GRAV_MIXED",
                    "n_obs": n, "n_prisms": M, "pairs_per_step": pairs},
         "roofline": roofline,

@@ -3,11 +3,11 @@
 Calls only ``oracle`` (and the seeded input generators in ``workloads``).
 Run from the repository root:  python tests/golden/make_golden.py [which ...]
 
-* config4_rows.npz : d = G m at 2,000 seeded observation rows of the
+* paper_scale_rows.npz : d = G m at 2,000 seeded observation rows of the
   178,797 x 3,307,500 paper-scale workload (seed 12345 picks the rows),
   (G^T v) at 48 seeded cells for the workload's probe vector v, and the
   absolute term scale of those cells (tolerance of the FP32 edge terms).
-* config2_rows.npz : the same at 256 rows and 64 cells of the 10,000 x
+* ellipsoids_100x100x50_rows.npz : the same at 256 rows and 64 cells of the 10,000 x
   500,000 forward/adjoint workload, plus the corner-term scale (tolerance of
   the FP64 node evaluation).
 """
@@ -36,24 +36,24 @@ def _adjoint_cells_parallel(mesh, obs, v, cells, workers):
     return np.concatenate(parts)
 
 
-def make_config4(workers):
-    p = workloads.config4()
+def make_paper_scale(workers):
+    p = workloads.paper_scale()
     rng = np.random.default_rng(12345)
     rows = np.sort(rng.choice(p.obs.n, 2000, replace=False))
     cells = np.sort(rng.choice(p.mesh.ncells, 48, replace=False))
     t = time.time()
     d = parallel.forward_rows(p.mesh, p.obs, p.m, rows, workers=workers)
-    print(f"config4 rows: {time.time() - t:.1f} s", flush=True)
+    print(f"paper_scale rows: {time.time() - t:.1f} s", flush=True)
     t = time.time()
     g = _adjoint_cells_parallel(p.mesh, p.obs, p.probe_v, cells, workers)
     g_abs = prism.adjoint_abs_scale(p.mesh, p.obs, p.probe_v, cells)
-    print(f"config4 cells: {time.time() - t:.1f} s", flush=True)
-    np.savez(os.path.join(HERE, "config4_rows.npz"), rows=rows, d=d, cells=cells, gtv=g,
+    print(f"paper_scale cells: {time.time() - t:.1f} s", flush=True)
+    np.savez(os.path.join(HERE, "paper_scale_rows.npz"), rows=rows, d=d, cells=cells, gtv=g,
              gtv_abs=g_abs)
 
 
-def make_config2(workers):
-    p = workloads.config2()
+def make_ellipsoids(workers):
+    p = workloads.ellipsoids_100x100x50()
     rng = np.random.default_rng(2222)
     rows = np.sort(rng.choice(p.obs.n, 256, replace=False))
     cells = np.sort(rng.choice(p.mesh.ncells, 64, replace=False))
@@ -62,15 +62,15 @@ def make_config2(workers):
     g = _adjoint_cells_parallel(p.mesh, p.obs, p.probe_v, cells, workers)
     g_abs = prism.adjoint_abs_scale(p.mesh, p.obs, p.probe_v, cells)
     g_abs8 = prism.adjoint_abs_scale_corners(p.mesh, p.obs, p.probe_v, cells)
-    print(f"config2: {time.time() - t:.1f} s", flush=True)
-    np.savez(os.path.join(HERE, "config2_rows.npz"), rows=rows, d=d, cells=cells, gtv=g,
+    print(f"ellipsoids_100x100x50: {time.time() - t:.1f} s", flush=True)
+    np.savez(os.path.join(HERE, "ellipsoids_100x100x50_rows.npz"), rows=rows, d=d, cells=cells, gtv=g,
              gtv_abs=g_abs, gtv_abs_corners=g_abs8)
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config2", "config4"]
+    which = sys.argv[1:] or ["ellipsoids_100x100x50", "paper_scale"]
     w = parallel.default_workers()
-    if "config2" in which:
-        make_config2(w)
-    if "config4" in which:
-        make_config4(w)
+    if "ellipsoids_100x100x50" in which:
+        make_ellipsoids(w)
+    if "paper_scale" in which:
+        make_paper_scale(w)

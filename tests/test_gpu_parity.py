@@ -84,13 +84,13 @@ def test_forward_random_ragged(g, ctx, prec_name, case):
 
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
-def test_forward_config1(g, ctx, prec_name):
-    p = workloads.config1()
+def test_forward_dykes_32x32x16(g, ctx, prec_name):
+    p = workloads.dykes_32x32x16()
     mesh, obs = _dev(g, p)
     d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=getattr(g, prec_name)))
     ref = prism.forward(p.mesh, p.obs, p.m)
     err = rel_l2(d, ref)
-    _report(f"forward config1 {prec_name}", err)
+    _report(f"forward dykes_32x32x16 {prec_name}", err)
     assert err <= (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED)
     assert np.max(np.abs(d - ref)) <= 10 * (TOL_F64 if prec_name == "GRAV_FP64" else TOL_MIXED) * np.max(np.abs(ref))
 
@@ -215,8 +215,8 @@ def test_trace_and_diagonal(g, ctx, prec_name):
 
 # ------------------------------------------------------------------ inversion
 
-def _config1_reference():
-    p = workloads.config1()
+def _dykes_reference():
+    p = workloads.dykes_32x32x16()
     G = np.stack([prism.sensitivity_row(p.mesh, p.obs.x[o], p.obs.y[o], p.obs.z[o])
                   for o in range(p.obs.n)])
     cov = inversion.covariance_from_weights(p.wdepth)
@@ -229,41 +229,41 @@ def _config1_reference():
 
 
 @pytest.fixture(scope="module")
-def config1_ref():
-    return _config1_reference()
+def dykes_ref():
+    return _dykes_reference()
 
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
-def test_invert_config1_vs_cholesky(g, ctx, config1_ref, prec_name):
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+def test_invert_dykes_32x32x16_vs_cholesky(g, ctx, dykes_ref, prec_name):
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     m, d_pred, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=p.cg_tol,
                                  max_iter=2000, want_pred=True, prec=getattr(g, prec_name))
-    print(f"[parity] invert config1 {prec_name}: {info}", flush=True)
+    print(f"[parity] invert dykes_32x32x16 {prec_name}: {info}", flush=True)
     assert info["converged"] and info["relres"] <= p.cg_tol
     assert abs(info["trace"] - trace) <= 1e-5 * trace
     err = rel_l2(to_np(m), m_chol)
-    _report(f"invert config1 {prec_name} density", err)
+    _report(f"invert dykes_32x32x16 {prec_name} density", err)
     assert err <= 1e-4
     assert rel_l2(to_np(d_pred), G @ m_chol) <= 1e-4
 
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
-def test_invert_jacobi_preconditioned(g, ctx, config1_ref, prec_name):
+def test_invert_jacobi_preconditioned(g, ctx, dykes_ref, prec_name):
     """Jacobi-preconditioned CG (M = diag(G C G^T) + lambda I) reaches the same
     unique solution of Eq. 11 as the Cholesky solve."""
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     prec = getattr(g, prec_name)
     _, _, plain = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=p.cg_tol,
                              max_iter=2000, prec=prec)
     m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=p.cg_tol,
                             max_iter=2000, prec=prec, precond=1)
-    print(f"[parity] invert config1 {prec_name} Jacobi: {info['iters']} iterations "
+    print(f"[parity] invert dykes_32x32x16 {prec_name} Jacobi: {info['iters']} iterations "
           f"(plain CG {plain['iters']})", flush=True)
     assert info["converged"] and info["relres"] <= p.cg_tol
     err = rel_l2(to_np(m), m_chol)
-    _report(f"invert config1 {prec_name} Jacobi density", err)
+    _report(f"invert dykes_32x32x16 {prec_name} Jacobi density", err)
     assert err <= 1e-4
 
 
@@ -275,9 +275,9 @@ def test_invert_jacobi_preconditioned(g, ctx, config1_ref, prec_name):
 _EARLY = 8
 
 
-def test_invert_misfit_history_plain_cg(g, ctx, config1_ref):
+def test_invert_misfit_history_plain_cg(g, ctx, dykes_ref):
     """Misfit log of plain CG against the oracle's residual history."""
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     cov = inversion.covariance_from_weights(p.wdepth)
     A = inversion.dataspace_matrix(G, cov, lam)
@@ -293,13 +293,13 @@ def test_invert_misfit_history_plain_cg(g, ctx, config1_ref):
     assert len(h) == full["iters"] and h[-1] == full["relres"] <= 1e-6 < min(h[:-1])
 
 
-def test_invert_warm_start_and_resume(g, ctx, config1_ref):
+def test_invert_warm_start_and_resume(g, ctx, dykes_ref):
     """Warm start / resume: CG from an oracle iterate (10 oracle iterations)
     follows the oracle's resumed history and returns its final iterate in
     y_out; from the Cholesky solution no iteration is needed; the restarted
     policy resumes the same way."""
     import torch
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     cov = inversion.covariance_from_weights(p.wdepth)
     A = inversion.dataspace_matrix(G, cov, lam)
@@ -326,8 +326,8 @@ def test_invert_warm_start_and_resume(g, ctx, config1_ref):
     assert rel_l2(to_np(m3), cov * (G.T @ y_r)) <= 2e-5
 
 
-def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+def test_invert_fixed_iterations_and_noconv(g, ctx, dykes_ref):
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     m, _, info = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=lam, fixed_iters=5)
     assert info["iters"] == 5 and info["converged"]
@@ -344,11 +344,11 @@ def test_invert_fixed_iterations_and_noconv(g, ctx, config1_ref):
 
 @pytest.mark.parametrize("prec_name,tol", [("GRAV_FP64", 1e-4), ("GRAV_FP64", 1e-6),
                                            ("GRAV_MIXED", 1e-4)])
-def test_invert_restarted_policy(g, ctx, config1_ref, prec_name, tol):
+def test_invert_restarted_policy(g, ctx, dykes_ref, prec_name, tol):
     """Restarted CG (Section 2.2 policy: at most 20 inner iterations in at most
     30 cycles, step backtracking) against the oracle's restarted CG on the
     dense system of Eq. 11."""
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     cov = inversion.covariance_from_weights(p.wdepth)
     A = inversion.dataspace_matrix(G, cov, lam)
@@ -375,12 +375,12 @@ def test_invert_restarted_policy(g, ctx, config1_ref, prec_name, tol):
     n_early, early = (_EARLY, 1e-6) if prec_name == "GRAV_FP64" else (4, 1e-3)
     np.testing.assert_allclose(hlog[:n_early], log[:n_early], rtol=early)
     err = rel_l2(to_np(m), m_ref)
-    _report(f"restarted CG config1 {prec_name} tol {tol} vs oracle", err)
+    _report(f"restarted CG dykes_32x32x16 {prec_name} tol {tol} vs oracle", err)
     assert rel_l2(to_np(m), m_chol) <= 10 * tol and err <= 20 * tol
 
 
-def test_invert_restarted_cycle_cap_and_errors(g, ctx, config1_ref):
-    p, G, d_obs, trace, lam, m_chol = config1_ref
+def test_invert_restarted_cycle_cap_and_errors(g, ctx, dykes_ref):
+    p, G, d_obs, trace, lam, m_chol = dykes_ref
     mesh, obs = _dev(g, p)
     cov = inversion.covariance_from_weights(p.wdepth)
     A = inversion.dataspace_matrix(G, cov, lam)
@@ -417,41 +417,41 @@ def test_invert_with_reference_model(g, ctx):
 
 # ------------------------------------------------------------------ full-size workloads
 
-def test_config2_forward_adjoint_sampled(g, ctx):
-    p = workloads.config2()
-    gold = np.load(os.path.join(HERE, "golden", "config2_rows.npz"))
+def test_ellipsoids_100x100x50_forward_adjoint_sampled(g, ctx):
+    p = workloads.ellipsoids_100x100x50()
+    gold = np.load(os.path.join(HERE, "golden", "ellipsoids_100x100x50_rows.npz"))
     mesh, obs = _dev(g, p)
     for prec_name, tol in (("GRAV_MIXED", TOL_MIXED), ("GRAV_FP64", TOL_F64)):
         prec = getattr(g, prec_name)
         d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=prec))
         err = rel_l2(d[gold["rows"]], gold["d"])
-        _report(f"config2 forward {prec_name} (256 rows)", err)
+        _report(f"ellipsoids_100x100x50 forward {prec_name} (256 rows)", err)
         assert err <= tol
         gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=prec))
         if prec_name == "GRAV_FP64":
             # corner terms ~R ln R, each within a few ulp: C_TERMS * eps64 * sum |terms|
             got, ref = gt[gold["cells"]], gold["gtv"]
             ratio = np.abs(got - ref) / (C_TERMS * 2.0 ** -53 * gold["gtv_abs_corners"])
-            print(f"[parity] config2 adjoint GRAV_FP64 (64 cells): rel L2 = {rel_l2(got, ref):.3e}, "
+            print(f"[parity] ellipsoids_100x100x50 adjoint GRAV_FP64 (64 cells): rel L2 = {rel_l2(got, ref):.3e}, "
                   f"worst err / term bound = {ratio.max():.3f}", flush=True)
             assert np.all(ratio <= 1.0)
         else:
-            _check_termwise(f"config2 adjoint {prec_name} (64 cells)", gt[gold["cells"]], gold["gtv"],
+            _check_termwise(f"ellipsoids_100x100x50 adjoint {prec_name} (64 cells)", gt[gold["cells"]], gold["gtv"],
                             gold["gtv_abs"])
 
 
-def test_config4_forward_sampled_rows(g, ctx):
+def test_paper_scale_forward_sampled_rows(g, ctx):
     """Paper-scale G m (178,797 x 3,307,500) in the launch configuration the
     benchmark times, checked on 2,000 seeded rows computed by the oracle."""
-    p = workloads.config4()
-    gold = np.load(os.path.join(HERE, "golden", "config4_rows.npz"))
+    p = workloads.paper_scale()
+    gold = np.load(os.path.join(HERE, "golden", "paper_scale_rows.npz"))
     mesh, obs = _dev(g, p)
     d = to_np(ctx.forward(mesh, obs, _t(p.m), prec=g.GRAV_MIXED))
     err = rel_l2(d[gold["rows"]], gold["d"])
-    _report("config4 forward GRAV_MIXED (2000 rows)", err)
+    _report("paper_scale forward GRAV_MIXED (2000 rows)", err)
     assert err <= TOL_MIXED
     gt = to_np(ctx.adjoint(mesh, obs, _t(p.probe_v), prec=g.GRAV_MIXED))
-    _check_termwise("config4 adjoint GRAV_MIXED (48 cells)", gt[gold["cells"]], gold["gtv"],
+    _check_termwise("paper_scale adjoint GRAV_MIXED (48 cells)", gt[gold["cells"]], gold["gtv"],
                     gold["gtv_abs"])
 
 
@@ -489,12 +489,12 @@ def test_forward_multi_per_model(g, ctx, prec_name, case):
     assert np.all(errs <= TOL_MULTI)
 
 
-def test_forward_multi_config3_sampled_rows(g, ctx):
+def test_forward_multi_box_models_sampled_rows(g, ctx):
     """64 models on the 500k-cell mesh with 10,000 observations; 48 seeded rows
     per model against the FP64 oracle, for both contraction paths."""
     import torch
-    p = workloads.config2()
-    models = workloads.config3_models(p.mesh).astype(np.float32)
+    p = workloads.ellipsoids_100x100x50()
+    models = workloads.smoothed_box_models(p.mesh).astype(np.float32)
     rows = np.sort(np.random.default_rng(333).choice(p.obs.n, 48, replace=False))
     ref = prism.forward_multi(p.mesh, p.obs, models.astype(np.float64), rows=rows)
     mesh, obs = _dev(g, p)
@@ -502,7 +502,7 @@ def test_forward_multi_config3_sampled_rows(g, ctx):
     for prec_name in ("GRAV_MIXED_BF16X3", "GRAV_FP32_VALU"):
         D = to_np(ctx.forward_multi(mesh, obs, mt, prec=getattr(g, prec_name)))[rows]
         errs = np.linalg.norm(D - ref, axis=0) / np.linalg.norm(ref, axis=0)
-        print(f"[parity] config3 multi {prec_name}: per-model rel L2 max {errs.max():.2e} "
+        print(f"[parity] box models multi {prec_name}: per-model rel L2 max {errs.max():.2e} "
               f"median {np.median(errs):.2e}", flush=True)
         assert np.all(errs <= TOL_MULTI)
 

@@ -166,7 +166,7 @@ def test_serving_stream_largest_requests_sampled():
     match the FP64 oracle on sampled stations, and the inversions finish."""
     import torch
     pkg = load_package()
-    reqs = workloads.config5_stream()
+    reqs = workloads.serving_stream()
     fwd = max((r for r in reqs if r["kind"] == "forward"),
               key=lambda r: r["n_target"] * r["cells_target"])
     invs = sorted((r for r in reqs if r["kind"] == "inversion"),

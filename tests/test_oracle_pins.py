@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import GAMMA, prism, inversion, trend
-from workloads import Mesh, Survey, random_case, regular_mesh, config1
+from workloads import Mesh, Survey, random_case, regular_mesh, dykes_32x32x16
 
 
 def _one_prism(x0, x1, y0, y1, z0, z1):
@@ -366,9 +366,9 @@ def test_noise_model_relative_rms_and_r2_scaling():
     assert 3.0 < (1 - 0.9986) / (1 - 0.9996) < 4.0
 
 
-def test_config1_model_geometry():
+def test_dykes_32x32x16_model_geometry():
     """Input recipe check: both dykes are 2 cells wide, 8 long, 10 deep."""
-    p = config1()
+    p = dykes_32x32x16()
     assert p.mesh.ncells == 16384 and p.obs.n == 1024
     assert int((p.m > 0).sum()) == 320
     assert np.all(p.obs.z == p.mesh.zn[0])

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Mesh", "Survey", "Problem", "regular_mesh", "cell_centres",
-    "config1", "config2", "config3_models", "config4", "config5_stream",
+    "dykes_32x32x16", "ellipsoids_100x100x50", "smoothed_box_models", "paper_scale", "serving_stream",
     "random_case", "ellipsoid_model", "dyke_model",
 ]
 
@@ -189,7 +189,7 @@ def dyke_model(mesh: Mesh, vertical: dict, dipping: dict, rho: float) -> np.ndar
 # Named workloads
 # --------------------------------------------------------------------------
 
-def config1() -> Problem:
+def dykes_32x32x16() -> Problem:
     """Tiny plain-FP64 inversion case: 32x32 observation grid on the mesh top
     (50 m spacing, at cell-centre x,y) over a 32x32x16 mesh of 50 m cubes;
     vertical dyke 100x400x500 m plus a 45-degree dipping dyke, +300 kg/m^3;
@@ -204,12 +204,12 @@ def config1() -> Problem:
     OX, OY = np.meshgrid(xc, yc, indexing="ij")
     obs = Survey(OX.ravel(), OY.ravel(), np.zeros(OX.size))
     rng = np.random.default_rng(1)
-    return Problem("config1", mesh, obs, m, wdepth=depth_weights(mesh, 25.0),
+    return Problem("dykes_32x32x16", mesh, obs, m, wdepth=depth_weights(mesh, 25.0),
                    noise_draws=rng.standard_normal(obs.n), noise_level=0.01,
                    cg_tol=1e-6, cg_iters=0)
 
 
-def config2() -> Problem:
+def ellipsoids_100x100x50() -> Problem:
     """Forward/adjoint case: 100x100 observation grid (25 m spacing, cell-centre
     x,y) at random heights U[0,50] m over a 100x100x50 mesh of 25 m cubes;
     density = 20 random ellipsoids, contrast U[-400,400] kg/m^3 (seed 0);
@@ -222,10 +222,10 @@ def config2() -> Problem:
     obs = Survey(OX.ravel(), OY.ravel(), mesh.zn[0] - h)
     m = ellipsoid_model(mesh, rng, 20, 50.0, 625.0)
     v = np.random.default_rng(2).standard_normal(obs.n)
-    return Problem("config2", mesh, obs, m, probe_v=v)
+    return Problem("ellipsoids_100x100x50", mesh, obs, m, probe_v=v)
 
 
-def config3_models(mesh: Mesh, count: int = 64, first_seed: int = 100) -> np.ndarray:
+def smoothed_box_models(mesh: Mesh, count: int = 64, first_seed: int = 100) -> np.ndarray:
     """Block of density models for the multi-model forward: model j (seed
     first_seed + j) = 5 random axis-aligned boxes (sides U[75,750] m, contrast
     U[-400,400]) plus N(0,1) white noise smoothed by a 3-D Gaussian of sigma =
@@ -253,7 +253,7 @@ def config3_models(mesh: Mesh, count: int = 64, first_seed: int = 100) -> np.nda
     return out
 
 
-def config4(n_obs: int = 178_797) -> Problem:
+def paper_scale(n_obs: int = 178_797) -> Problem:
     """Paper-scale case: 178,797 observations scattered uniformly over a
     15x15 km area (seed 4) at heights of a synthetic Gaussian-bump topography
     (max 300 m) over a 150x150x147 mesh of 100x100x70 m cells (3,307,500
@@ -279,11 +279,11 @@ def config4(n_obs: int = 178_797) -> Problem:
     m += ellipsoid_model(mesh, rng, 10, 300.0, 2500.0)
     noise = rng.standard_normal(n_obs)
     v = np.random.default_rng(40).standard_normal(n_obs)
-    return Problem("config4", mesh, obs, m, wdepth=depth_weights(mesh, 25.0),
+    return Problem("paper_scale", mesh, obs, m, wdepth=depth_weights(mesh, 25.0),
                    noise_draws=noise, noise_level=0.02, probe_v=v, cg_iters=50)
 
 
-def config5_stream(n_requests: int = 200, mean_gap_s: float = 0.5, seed: int = 5,
+def serving_stream(n_requests: int = 200, mean_gap_s: float = 0.5, seed: int = 5,
                    n_lo: int = 1000, n_hi: int = 40000,
                    cells_lo: int = 50_000, cells_hi: int = 800_000):
     """Serving stream: Poisson arrivals (exponential gaps, mean 0.5 s), each a
