@@ -73,14 +73,8 @@ struct AdjJob {
 };
 
 // Pointers read from a job table are generic pointers to the compiler, so
-// loads through them would go through the flat path in vector registers.
-// They all point to device global memory: casting through the global address
-// space lets the compiler use global (and, for wave-uniform addresses, scalar)
-// loads, as it does for the kernel arguments of the single-call kernels.
-template <typename T>
-__device__ __forceinline__ T *global_ptr(T *p) {
-    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
-}
+// loads through them would go through the flat path in vector registers; they
+// all point to device global memory and pass through global_ptr().
 
 template <typename Job>
 __device__ __forceinline__ int find_job(const Job *__restrict__ jobs, int njobs, int64_t vb) {
@@ -105,8 +99,9 @@ __global__ __launch_bounds__(kBlock) void k_forward_batched(const FwdJob *__rest
                         local / j.nchunk, global_ptr(j.partial));
 }
 
-__global__ __launch_bounds__(kBlock) void k_adjoint_batched(const AdjJob *__restrict__ jobs, int njobs,
-                                                            int64_t base) {
+// Bounded to 8 waves per SIMD like the single-call adjoint sweep.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_adjoint_batched(const AdjJob *__restrict__ jobs, int njobs, int64_t base) {
     const int64_t vb = base + blockIdx.x;
     const AdjJob &j = jobs[find_job(jobs, njobs, vb)];
     int64_t local = vb - j.block_begin;

@@ -8,6 +8,15 @@
 
 namespace grav {
 
+// A pointer the compiler sees as generic (read from memory, or made opaque)
+// but which points to device global memory: casting it through the global
+// address space lets the compiler use global loads and, for wave-uniform
+// addresses, scalar loads instead of the flat path.
+template <typename T>
+__device__ __forceinline__ T *global_ptr(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 // Depth below the observation of node c of a column, Z_c - z_o, as the FP32 sum
 // of (Z_c - Z_0) from the layer table and ztop = Z_0 - z_o: both terms are
 // non-negative FP64 differences rounded to FP32, so the sum has no
@@ -79,32 +88,69 @@ __device__ __forceinline__ void forward_mixed_block(
 }
 
 // One observation's contribution to a lane's layer chunk of the adjoint:
-// layers k0 .. k0 + cnt - 1 (cnt <= kAdjLayers; the guard on j < cnt is
-// uniform across the block).
+// layers k0 .. k0 + cnt - 1 (1 <= cnt <= kAdjLayers, uniform across the
+// block), two layers per step.  The thickness and node depth of the next two
+// layers are loaded while the current two compute (indices clamped to the
+// chunk's last layer), so each step waits only on loads issued a step earlier;
+// the two layers of a step share one guard and need no register copies
+// between them.
+static_assert(kAdjLayers % 2 == 0, "the adjoint steps two layers at a time");
+
 template <bool kDeep>
 __device__ __forceinline__ void adjoint_obs(double X, double Y, const float *__restrict__ zrel,
-                                            double zn0, int k0, int cnt,
-                                            const float (&h)[kAdjLayers], double xo, double yo,
-                                            double zo, double vo, double (&acc)[kAdjLayers]) {
+                                            const float *__restrict__ hk, double zn0, int k0,
+                                            int cnt, double xo, double yo, double zo, double vo,
+                                            double (&acc)[kAdjLayers]) {
     const Column c = make_column(X, Y, xo, yo);
     const float ztop = static_cast<float>(zn0 - zo);
     Node top = make_node(c, node_depth(zrel, k0, ztop));
+    const int kl = k0 + cnt - 1;
+    float za = zrel[k0], zb = zrel[k0 + 1 <= kl ? k0 + 1 : kl];
+    float ha = hk[k0], hb = hk[k0 + 1 <= kl ? k0 + 1 : kl];
 #pragma unroll
-    for (int j = 0; j < kAdjLayers; ++j) {
+    for (int j = 0; j < kAdjLayers; j += 2) {
         if (j < cnt) {
-            const Node bot = make_node(c, zrel[k0 + j] + ztop);
-            const float S = edge_segment<kDeep>(c, top, bot, h[j]);
-            acc[j] = fma(vo, static_cast<double>(S), acc[j]);
-            top = bot;
+            const float z1 = za, z2 = zb, h1 = ha, h2 = hb;
+            const int n1 = k0 + j + 2 <= kl ? k0 + j + 2 : kl;
+            const int n2 = k0 + j + 3 <= kl ? k0 + j + 3 : kl;
+            za = zrel[n1]; zb = zrel[n2]; ha = hk[n1]; hb = hk[n2];
+            const Node b1 = make_node(c, z1 + ztop);
+            const float S1 = edge_segment<kDeep>(c, top, b1, h1);
+            acc[j] = fma(vo, static_cast<double>(S1), acc[j]);
+            if (j + 1 < cnt) {
+                const Node b2 = make_node(c, z2 + ztop);
+                const float S2 = edge_segment<kDeep>(c, b1, b2, h2);
+                acc[j + 1] = fma(vo, static_cast<double>(S2), acc[j + 1]);
+                top = b2;
+            }
         }
     }
 }
 
+// The observation loop of one lane.  The layer count and the two table
+// pointers pass through an empty asm statement once per observation: the
+// compiler can no longer hoist the per-layer loads out of the loop, where they
+// would hold 2 * kAdjLayers scalar registers and cut the waves per SIMD.
+template <bool kDeep>
+__device__ __forceinline__ void adjoint_obs_range(
+    double X, double Y, const float *__restrict__ zrel, const float *__restrict__ hk, double zn0,
+    int k0, int cnt, const double *__restrict__ ox, const double *__restrict__ oy,
+    const double *__restrict__ oz, const double *__restrict__ v, int64_t o0, int64_t o1,
+    double (&acc)[kAdjLayers]) {
+    for (int64_t o = o0; o < o1; ++o) {
+        int cnt_o = cnt;
+        const float *zr_o = zrel, *hk_o = hk;
+        asm volatile("" : "+s"(cnt_o), "+s"(zr_o), "+s"(hk_o));
+        adjoint_obs<kDeep>(X, Y, global_ptr(zr_o), global_ptr(hk_o), zn0, k0, cnt_o, ox[o], oy[o],
+                           oz[o], v[o], acc);
+    }
+}
+
 // Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane and
-// layer chunk kc of nkc (nkc = ceil(nz / kAdjLayers) chunks of near-equal
-// length, at most kAdjLayers layers each), observations of part `part`;
-// writes upart[part][segment] = sum_{o in part} v_o S (FP64, one register
-// pair per layer, no cross-lane reduction).
+// layer chunk kc of nkc (nkc = ceil(nz / kAdjLayers) chunks: the first
+// nz mod nkc hold one layer more than the others), observations of part
+// `part`; writes upart[part][segment] = sum_{o in part} v_o S (FP64, one
+// register pair per layer, no cross-lane reduction).
 __device__ __forceinline__ void adjoint_mixed_block(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
@@ -113,29 +159,31 @@ __device__ __forceinline__ void adjoint_mixed_block(
     double *__restrict__ upart) {
     const int64_t col = colblk * kBlock + threadIdx.x;
     const int64_t colc = col < ncols ? col : ncols - 1;
-    const int a = (int)(colc / ny1);
-    const int b = (int)(colc - (int64_t)a * ny1);
+    int a, b;
+    if (ncols <= 0x7fffffff) {   // 32-bit division when the column index fits
+        const unsigned cu = (unsigned)colc;
+        a = (int)(cu / (unsigned)ny1);
+        b = (int)(cu - (unsigned)a * (unsigned)ny1);
+    } else {
+        a = (int)(colc / ny1);
+        b = (int)(colc - (int64_t)a * ny1);
+    }
     const double X = xn[a], Y = yn[b];
-    const int k0 = (int)((int64_t)kc * nz / nkc);
-    const int cnt = (int)((int64_t)(kc + 1) * nz / nkc) - k0;
+    const int kq = nz / nkc, kr = nz - kq * nkc;
+    const int k0 = kc * kq + (kc < kr ? kc : kr);
+    const int cnt = kq + (kc < kr ? 1 : 0);
     const float *__restrict__ zrel = hk + nz + 1;
     const double zn0 = zn[0];
-    float h[kAdjLayers];
-#pragma unroll
-    for (int j = 0; j < kAdjLayers; ++j) h[j] = j < cnt ? hk[k0 + j] : 1.0f;
     double acc[kAdjLayers];
 #pragma unroll
     for (int j = 0; j < kAdjLayers; ++j) acc[j] = 0.0;
     const int64_t o0 = (int64_t)part * obs_per_part;
     const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
     const bool deep = k0 >= reinterpret_cast<const int *>(hk + nz)[0];   // uniform per block
-    if (deep) {
-        for (int64_t o = o0; o < o1; ++o)
-            adjoint_obs<true>(X, Y, zrel, zn0, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
-    } else {
-        for (int64_t o = o0; o < o1; ++o)
-            adjoint_obs<false>(X, Y, zrel, zn0, k0, cnt, h, ox[o], oy[o], oz[o], v[o], acc);
-    }
+    if (deep)
+        adjoint_obs_range<true>(X, Y, zrel, hk, zn0, k0, cnt, ox, oy, oz, v, o0, o1, acc);
+    else
+        adjoint_obs_range<false>(X, Y, zrel, hk, zn0, k0, cnt, ox, oy, oz, v, o0, o1, acc);
     if (col < ncols) {
         double *__restrict__ dst = upart + (int64_t)part * ncols * nz + col * nz + k0;
 #pragma unroll

@@ -211,17 +211,20 @@ __global__ __launch_bounds__(kBlock) void k_forward_f64(
 }
 
 // Mixed adjoint sweep.  Lane = (node column, chunk of <= kAdjLayers layers).
-__global__ __launch_bounds__(kBlock) void k_adjoint_mixed(
+// Bounded to 64 VGPRs so that 8 waves fit on a SIMD (the few values it spills
+// are read once per observation, outside the layer steps).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_adjoint_mixed(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
     const double *__restrict__ oy, const double *__restrict__ oz, const double *__restrict__ v,
     int64_t n, int64_t obs_per_part, int nparts, int64_t ncols, int nkc,
     double *__restrict__ upart) {
-    int64_t bid = blockIdx.x;
-    const int part = (int)(bid % nparts);
-    bid /= nparts;
-    const int kc = (int)(bid % nkc);
-    bid /= nkc;
+    unsigned bid = blockIdx.x;
+    const int part = (int)(bid % (unsigned)nparts);
+    bid /= (unsigned)nparts;
+    const int kc = (int)(bid % (unsigned)nkc);
+    bid /= (unsigned)nkc;
     adjoint_mixed_block(xn, yn, zn, ny1, nz, hk, ox, oy, oz, v, n, obs_per_part, ncols, nkc, part,
                         kc, bid, upart);
 }
