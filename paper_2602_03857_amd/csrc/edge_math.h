@@ -99,11 +99,13 @@ __device__ __forceinline__ float atan_small(float d) {
     return p * d;
 }
 
-// log1p(t) for t >= 0.
+// log1p(t) for t >= 0.  kBelowOne: the caller guarantees t < 1, so u < 2 and
+// the clamp of 2 - u at zero never acts (same result, one instruction less).
+template <bool kBelowOne = false>
 __device__ __forceinline__ float log1p_pos(float t) {
     const float u = 1.0f + t;
     const float c = t - (u - 1.0f);
-    const float w = fmaxf(2.0f - u, 0.0f);
+    const float w = kBelowOne ? 2.0f - u : fmaxf(2.0f - u, 0.0f);
     return fmaf(log2(u), kLn2, c * w);
 }
 
@@ -178,7 +180,11 @@ __device__ __forceinline__ Node make_node(const Column &c, float z) {
 // the atan-difference argument obeys |delta| <= h (z1 + h) / z1^2 (bound from
 // z1 R1 + z2 R2 >= (z1 + z2) R1, x^2 + y^2 + z1^2 + z2^2 <= 2 R2^2, AM-GM on the
 // denominator and R2/R1 <= z2/z1), such layers have |delta| <= 10/81 < 1/8 for
-// all observations and take atan_small without range reduction.
+// all observations and take atan_small without range reduction.  The log1p
+// arguments there stay below 1 as well: dR / (R1 + |y|) <= h / z1, and for
+// y < 0, dR (R1 + |y|) / (x^2 + z1^2) = dR / (R1 - |y|) <= (z2^2 - z1^2) / z1^2
+// = 2 h / z1 + (h / z1)^2 (using R1 - |y| >= z1^2 / (2 R1) and R2 >= R1), at
+// most 2/9 + 1/81 when z1 >= 9 h; likewise for x.
 template <bool kDeep = false>
 __device__ __forceinline__ float edge_segment(const Column &c, const Node &t, const Node &b,
                                               float h) {
@@ -197,8 +203,8 @@ __device__ __forceinline__ float edge_segment(const Column &c, const Node &t, co
     const float numX = c.xneg ? rx : 1.0f;
     // dR/(R1 + y) and dR/(R1 + x) with dR = hz / (R1 + R2), one reciprocal
     const float q = hz * fm::rcp((t.R + b.R) * (denY * denX));
-    const float lnY = fm::log1p_pos(q * numY * denX);   // ln(R2 + y) - ln(R1 + y)
-    const float lnX = fm::log1p_pos(q * numX * denY);   // ln(R2 + x) - ln(R1 + x)
+    const float lnY = fm::log1p_pos<kDeep>(q * numY * denX);   // ln(R2 + y) - ln(R1 + y)
+    const float lnX = fm::log1p_pos<kDeep>(q * numX * denY);   // ln(R2 + x) - ln(R1 + x)
     // z2 atan(u2) - z1 atan(u1) = h atan(u2) + z1 atan(delta)
     const float at2 = fm::atan_ratio(c.xy, b.zR);
     const float num = -c.xy * hz * (c.s + t.zz + b.zz);
