@@ -36,15 +36,15 @@ import workloads  # noqa: E402
 # per second (FMA = one operation).  Algorithmic cost of one (observation,
 # vertical edge segment) pair: the minimal gfx950 instruction sequence of the
 # edge-segment formula (per-operation table in the design notes), 94
-# instructions for layers near the top and 76 for "deep" layers (top at least
+# instructions for layers near the top and 72 for "deep" layers (top at least
 # 9 thicknesses and 1 mm below the mesh top, where the atan difference needs no
 # range reduction, no limit select is needed and the log1p arguments stay
-# below 1).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log) and 2 are
+# below 1/4).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log) and 2 are
 # FP64.  Issue cost relative to an FP32 add, measured with --issue-probe
 # (dependent chains of one instruction class): a transcendental takes 2 slots,
 # an FP64 FMA 1; issue slots per pair = instructions + 6 * (2 - 1).
 PEAK_SLOTS = 157.3e12 / 2.0
-INSTR_SHALLOW, INSTR_DEEP = 94, 76
+INSTR_SHALLOW, INSTR_DEEP = 94, 72
 N_TRANS, N_FP64 = 6, 2
 TRANS_COST, FP64_COST = 2, 1
 DEEP_RATIO = 9.0

@@ -34,7 +34,10 @@
 //  * log1p(t), t >= 0: u = 1 + t rounded, c = t - (u - 1) its exact rounding
 //    error (Sterbenz), log1p(t) = ln(u) + c/u; c/u is replaced by
 //    c * max(0, 2 - u), which differs from it by less than 0.5 c for u <= 2
-//    and drops it above 2 where c/u < 2^-24 relative to ln(u) >= ln 2.
+//    and drops it above 2 where c/u < 2^-24 relative to ln(u) >= ln 2.  Where
+//    t < 1/4 is guaranteed (deep layers), c/u is replaced by c itself: the
+//    difference c (u - 1) / u is at most 2^-24 t, i.e. below 1.3 units in the
+//    last place of log1p(t) >= 0.8 t.
 //  * atan(n/d), d >= 0: r = min(|n|, d) / max(|n|, d) in [0, 1],
 //    atan(r) = r P(r^2) with a degree-8 polynomial in r^2 fitted to the
 //    relative error of atan on [0, 1] by iteratively reweighted least squares
@@ -99,14 +102,18 @@ __device__ __forceinline__ float atan_small(float d) {
     return p * d;
 }
 
-// log1p(t) for t >= 0.  kBelowOne: the caller guarantees t < 1, so u < 2 and
-// the clamp of 2 - u at zero never acts (same result, one instruction less).
-template <bool kBelowOne = false>
+// log1p(t) for t >= 0.  kSmall: the caller guarantees t < 1/4, and the
+// rounding error c of 1 + t is added without the 1/u factor (see the header).
+template <bool kSmall = false>
 __device__ __forceinline__ float log1p_pos(float t) {
     const float u = 1.0f + t;
     const float c = t - (u - 1.0f);
-    const float w = kBelowOne ? 2.0f - u : fmaxf(2.0f - u, 0.0f);
-    return fmaf(log2(u), kLn2, c * w);
+    if constexpr (kSmall) {
+        return fmaf(log2(u), kLn2, c);
+    } else {
+        const float w = fmaxf(2.0f - u, 0.0f);
+        return fmaf(log2(u), kLn2, c * w);
+    }
 }
 
 }  // namespace fm
@@ -181,7 +188,7 @@ __device__ __forceinline__ Node make_node(const Column &c, float z) {
 // z1 R1 + z2 R2 >= (z1 + z2) R1, x^2 + y^2 + z1^2 + z2^2 <= 2 R2^2, AM-GM on the
 // denominator and R2/R1 <= z2/z1), such layers have |delta| <= 10/81 < 1/8 for
 // all observations and take atan_small without range reduction.  The log1p
-// arguments there stay below 1 as well: dR / (R1 + |y|) <= h / z1, and for
+// arguments there stay below 1/4 as well: dR / (R1 + |y|) <= h / z1, and for
 // y < 0, dR (R1 + |y|) / (x^2 + z1^2) = dR / (R1 - |y|) <= (z2^2 - z1^2) / z1^2
 // = 2 h / z1 + (h / z1)^2 (using R1 - |y| >= z1^2 / (2 R1) and R2 >= R1), at
 // most 2/9 + 1/81 when z1 >= 9 h; likewise for x.
