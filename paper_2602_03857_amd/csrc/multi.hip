@@ -21,6 +21,8 @@
 // variant keeps steps 1-2 (G in FP32) and contracts on the vector ALUs.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "api_internal.h"
 #include "edge_math.h"
 
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     const int64_t oc = o < n ? o : n - 1;
     const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
     const float ztop = static_cast<float>(zn[0] - zo);
+    const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
     const int64_t b0 = (int64_t)chunk * blocks_per_chunk;
     const int64_t b1 = b0 + blocks_per_chunk < nblk ? b0 + blocks_per_chunk : nblk;
 
@@ -139,27 +142,35 @@ __global__ __launch_bounds__(256) void k_forward_multi(
         for (int k = 0; k < nz; ++k) {
             const float zb = static_cast<float>(zn[k + 1] - zo);
             const float h = hk[k];
-            // phase 1: edge terms of this layer
+            // phase 1: edge terms of this layer (deep layers, as in the
+            // single-model sweeps, take the shorter formula; k is uniform)
+            auto edge_terms = [&](auto deep) {
+                constexpr bool kDeep = decltype(deep)::value;
 #pragma unroll
-            for (int u = 0; u < kColsPerWave; ++u) {
-                const int c = wv + 4 * u;
-                if (c < kEdgeCols) {
-                    // recompute the column terms each layer rather than keeping
-                    // those of all seven columns live across the layer loop
-                    float xu = cx[u], yu = cy[u];
-                    asm volatile("" : "+v"(xu), "+v"(yu));
-                    const Column col = column_from_xy(xu, yu);
-                    Node top;
-                    top.z = zt;
-                    top.zz = zzt;
-                    top.R = cR[u];
-                    top.zR = zt * cR[u];
-                    const Node bot = make_node(col, zb);
-                    const float S = edge_segment(col, top, bot, h);
-                    sS[c][lo_] = valid[u] ? S : 0.0f;
-                    cR[u] = bot.R;
+                for (int u = 0; u < kColsPerWave; ++u) {
+                    const int c = wv + 4 * u;
+                    if (c < kEdgeCols) {
+                        // recompute the column terms each layer rather than keeping
+                        // those of all seven columns live across the layer loop
+                        float xu = cx[u], yu = cy[u];
+                        asm volatile("" : "+v"(xu), "+v"(yu));
+                        const Column col = column_from_xy(xu, yu);
+                        Node top;
+                        top.z = zt;
+                        top.zz = zzt;
+                        top.R = cR[u];
+                        top.zR = zt * cR[u];
+                        const Node bot = make_node(col, zb);
+                        const float S = edge_segment<kDeep>(col, top, bot, h);
+                        sS[c][lo_] = valid[u] ? S : 0.0f;
+                        cR[u] = bot.R;
+                    }
                 }
-            }
+            };
+            if (k >= kdeep)
+                edge_terms(std::true_type{});
+            else
+                edge_terms(std::false_type{});
             zt = zb;
             zzt = zb * zb;
             __syncthreads();
@@ -244,9 +255,19 @@ __global__ void k_reduce_multi(const double *__restrict__ partial, int nchunk, i
     }
 }
 
+// hk[k] = Z_{k+1} - Z_k; hk[nz] (as int) = first layer of the deep run: every
+// layer from it on has its top at least kDeepRatio thicknesses and
+// kDeepMinDepth below the mesh top.
 __global__ void k_layer_thickness_m(const double *__restrict__ zn, int nz, float *__restrict__ hk) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nz) hk[k] = static_cast<float>(zn[k + 1] - zn[k]);
+    if (k == 0) {
+        int kdeep = nz;
+        while (kdeep > 0 && (zn[kdeep - 1] - zn[0]) >= kDeepRatio * (zn[kdeep] - zn[kdeep - 1]) &&
+               (zn[kdeep - 1] - zn[0]) >= kDeepMinDepth)
+            --kdeep;
+        reinterpret_cast<int *>(hk + nz)[0] = kdeep;
+    }
 }
 
 struct MultiPlan {
