@@ -21,6 +21,8 @@
 // FP64 path.  The same regrouping over all three axes: node weight
 // W = B m (up to 8 cells per node, parity (-1)^(p+q+r) of Eq. 1) and
 // d_o = gamma * sum_nodes Psi(node - o) * W.
+#include <type_traits>
+
 #include "grav_internal.h"
 #include "edge_math.h"
 #include "sweep_bodies.h"
@@ -268,6 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_mixed(
     const int i1 = (int)(i0 + rows_per_chunk < nx ? i0 + rows_per_chunk : nx);
     const float ztop = static_cast<float>(zn[0] - zo);
     const float *__restrict__ zrel = hk + nz + 1;
+    const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
     double acc = 0.0;
     for (int i = i0; i < i1; ++i) {
         const double Xa = xn[i], Xb = xn[i + 1];
@@ -275,21 +278,30 @@ __global__ __launch_bounds__(kBlock) void k_trace_mixed(
             const float z1 = node_depth(zrel, k, ztop);
             const float z2 = node_depth(zrel, k + 1, ztop);
             const float h = hk[k];
-            Column ca = make_column(Xa, yn[0], xo, yo);
-            Column cb = make_column(Xb, yn[0], xo, yo);
-            float Sa = edge_segment(ca, make_node(ca, z1), make_node(ca, z2), h);
-            float Sb = edge_segment(cb, make_node(cb, z1), make_node(cb, z2), h);
-            for (int j = 0; j < ny; ++j) {
-                ca = make_column(Xa, yn[j + 1], xo, yo);
-                cb = make_column(Xb, yn[j + 1], xo, yo);
-                const float Sa1 = edge_segment(ca, make_node(ca, z1), make_node(ca, z2), h);
-                const float Sb1 = edge_segment(cb, make_node(cb, z1), make_node(cb, z2), h);
-                const double g = ((double)Sa - (double)Sb) - ((double)Sa1 - (double)Sb1);
-                const double w = wdepth[((int64_t)i * ny + j) * nz + k];
-                acc = fma(g * g, 1.0 / (w * w), acc);
-                Sa = Sa1;
-                Sb = Sb1;
-            }
+            // one row of prisms (i, all j, k); deep layers take the shorter
+            // edge formula (k is uniform, so the branch is too)
+            auto row = [&](auto deep) {
+                constexpr bool kDeep = decltype(deep)::value;
+                Column ca = make_column(Xa, yn[0], xo, yo);
+                Column cb = make_column(Xb, yn[0], xo, yo);
+                float Sa = edge_segment<kDeep>(ca, make_node(ca, z1), make_node(ca, z2), h);
+                float Sb = edge_segment<kDeep>(cb, make_node(cb, z1), make_node(cb, z2), h);
+                for (int j = 0; j < ny; ++j) {
+                    ca = make_column(Xa, yn[j + 1], xo, yo);
+                    cb = make_column(Xb, yn[j + 1], xo, yo);
+                    const float Sa1 = edge_segment<kDeep>(ca, make_node(ca, z1), make_node(ca, z2), h);
+                    const float Sb1 = edge_segment<kDeep>(cb, make_node(cb, z1), make_node(cb, z2), h);
+                    const double g = ((double)Sa - (double)Sb) - ((double)Sa1 - (double)Sb1);
+                    const double w = wdepth[((int64_t)i * ny + j) * nz + k];
+                    acc = fma(g * g, 1.0 / (w * w), acc);
+                    Sa = Sa1;
+                    Sb = Sb1;
+                }
+            };
+            if (k >= kdeep)
+                row(std::true_type{});
+            else
+                row(std::false_type{});
         }
     }
     if (o < n) partial[(int64_t)chunk * n + o] = acc;
