@@ -155,6 +155,9 @@ def test_single_prism_singular_and_far_positions(g, ctx, prec_name):
     dict(seed=5, nx=13, ny=11, nz=7, n=333, on_nodes=20, on_top=40),
     dict(seed=6, nx=31, ny=17, nz=19, n=70, on_nodes=5, on_top=5),
     dict(seed=7, nx=2, ny=3, nz=1, n=1, on_nodes=1, on_top=1),
+    # 40 layers, first deep layer 12: chunks of 14, 13, 13 layers starting at
+    # 0, 14, 27, the last two on the deep-layer path with an odd layer count
+    dict(seed=13, nx=9, ny=8, nz=40, n=61, on_nodes=5, on_top=5),
 ])
 def test_adjoint_random_ragged(g, ctx, prec_name, case):
     p = workloads.random_case(case["seed"], case["nx"], case["ny"], case["nz"], case["n"],
@@ -200,9 +203,13 @@ def test_dataspace_apply_matches_oracle(g, ctx, prec_name):
 
 
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
-def test_trace_and_diagonal(g, ctx, prec_name):
+@pytest.mark.parametrize("case", [
+    (10, 9, 14, 6, 129),
+    (11, 6, 7, 24, 97),    # first deep layer 10 of 24: both edge formulas
+])
+def test_trace_and_diagonal(g, ctx, prec_name, case):
     import torch
-    p = workloads.random_case(10, 9, 14, 6, 129, on_top=10, on_nodes=10)
+    p = workloads.random_case(*case, on_top=10, on_nodes=10)
     mesh, obs = _dev(g, p)
     cov = inversion.covariance_from_weights(p.wdepth)
     ref_diag = prism.weighted_row_sumsq(p.mesh, p.obs, cov)
