@@ -1,0 +1,70 @@
+"""Bounds that the deep-layer edge formula of the GPU sweeps relies on.
+
+In a layer whose top lies at least 9 thicknesses below the mesh top, every
+observation on or above the top sees z1 >= 9 h.  The deep-layer formula then
+(a) evaluates the atan of the difference term z1 atan(u1) -> atan(delta) with
+a short odd polynomial that is accurate for |delta| <= 1/8, and (b) adds the
+rounding error of 1 + t in log1p(t) without the 1/u factor, which is accurate
+for t < 1/4.  Both bounds are facts about the edge-segment formula (Eq. 1-3
+written as a difference over one vertical edge); this test samples them in
+FP64, including the worst cases (observation close to the column, one of x, y
+zero or negative, z1 at its smallest)."""
+import numpy as np
+
+DEEP_RATIO = 9.0
+
+
+def _terms(x, y, z1, h):
+    z2 = z1 + h
+    s = x * x + y * y
+    r1 = np.sqrt(s + z1 * z1)
+    r2 = np.sqrt(s + z2 * z2)
+    dr = h * (z1 + z2) / (r1 + r2)
+    # 1/(R1 + y) without cancellation: rationalised for y < 0
+    inv_y = np.where(y >= 0, 1.0 / (r1 + np.abs(y)), (r1 + np.abs(y)) / (x * x + z1 * z1))
+    inv_x = np.where(x >= 0, 1.0 / (r1 + np.abs(x)), (r1 + np.abs(x)) / (y * y + z1 * z1))
+    u1 = x * y / (z1 * r1)
+    u2 = x * y / (z2 * r2)
+    delta = (u2 - u1) / (1.0 + u1 * u2)
+    return dr * inv_y, dr * inv_x, delta
+
+
+def _samples(rng, n):
+    h = rng.uniform(1.0, 300.0, n)
+    z1 = h * (DEEP_RATIO + rng.exponential(3.0, n) * (rng.random(n) < 0.7))
+    scale = z1 * 10.0 ** rng.uniform(-3, 3, n)
+    x = rng.standard_normal(n) * scale
+    y = rng.standard_normal(n) * scale
+    # one offset zero, or both, in a share of the samples
+    x[rng.random(n) < 0.1] = 0.0
+    y[rng.random(n) < 0.1] = 0.0
+    return x, y, z1, h
+
+
+def test_log1p_arguments_below_a_quarter_in_deep_layers():
+    rng = np.random.default_rng(11)
+    x, y, z1, h = _samples(rng, 400_000)
+    ty, tx = _terms(x, y, z1, h)[:2]
+    bound = 2.0 / DEEP_RATIO + 1.0 / DEEP_RATIO ** 2
+    assert np.all(ty >= 0) and np.all(tx >= 0)
+    assert ty.max() <= bound * (1 + 1e-12) and tx.max() <= bound * (1 + 1e-12)
+    assert bound < 0.25
+    # the bound is approached: observation far along -y, x = 0, z1 = 9 h
+    hh = np.array([50.0])
+    t_edge = _terms(np.array([0.0]), np.array([-1e9]), DEEP_RATIO * hh, hh)[0][0]
+    assert t_edge > 0.99 * bound
+
+
+def test_atan_difference_below_an_eighth_in_deep_layers():
+    rng = np.random.default_rng(12)
+    x, y, z1, h = _samples(rng, 400_000)
+    delta = _terms(x, y, z1, h)[2]
+    assert np.abs(delta).max() <= 10.0 / 81.0 * (1 + 1e-12)
+    assert 10.0 / 81.0 < 0.125
+
+
+def test_bounds_fail_above_the_deep_threshold():
+    # at z1 = 2 h the log1p argument can exceed 1/4: the threshold matters
+    h = np.array([100.0])
+    t = _terms(np.array([0.0]), np.array([-1e9]), 2.0 * h, h)[0][0]
+    assert t > 0.25
