@@ -36,8 +36,9 @@
 //    c * max(0, 2 - u), which differs from it by less than 0.5 c for u <= 2
 //    and drops it above 2 where c/u < 2^-24 relative to ln(u) >= ln 2.  Where
 //    t < 1/4 is guaranteed (deep layers), c/u is replaced by c itself: the
-//    difference c (u - 1) / u is at most 2^-24 t, i.e. below 1.3 units in the
-//    last place of log1p(t) >= 0.8 t.
+//    difference |c| (u - 1) / u is zero for t <= 2^-24 (then u = 1) and at
+//    most 2^-24 (t + 2^-24) < 2^-23 t above, a relative error below 1.2e-7
+//    of log1p(t) >= 0.875 t (about 2^-24 once t >> 2^-24).
 //  * atan(n/d), d >= 0: r = min(|n|, d) / max(|n|, d) in [0, 1],
 //    atan(r) = r P(r^2) with a degree-8 polynomial in r^2 fitted to the
 //    relative error of atan on [0, 1] by iteratively reweighted least squares
@@ -103,7 +104,8 @@ __device__ __forceinline__ float atan_small(float d) {
 }
 
 // log1p(t) for t >= 0.  kSmall: the caller guarantees t < 1/4, and the
-// rounding error c of 1 + t is added without the 1/u factor (see the header).
+// rounding error c of 1 + t is added without the 1/u factor (error bound in
+// the header).
 template <bool kSmall = false>
 __device__ __forceinline__ float log1p_pos(float t) {
     const float u = 1.0f + t;

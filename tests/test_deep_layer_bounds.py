@@ -68,3 +68,32 @@ def test_bounds_fail_above_the_deep_threshold():
     h = np.array([100.0])
     t = _terms(np.array([0.0]), np.array([-1e9]), 2.0 * h, h)[0][0]
     assert t > 0.25
+
+
+def test_log1p_without_the_inverse_factor():
+    # u = fl32(1 + t), c = t - (u - 1) exact; ln(u) + c against log1p(t), with
+    # ln(u) taken exact so that only the dropped factor 1/u is measured.  The
+    # difference |c| (u - 1) / u is at most 2^-24 (t + 2^-24) < 2^-23 t (worst
+    # just above t = 2^-24, where u rounds up to 1 + 2^-23), and about
+    # 2^-24 t once t >> 2^-24.
+    rng = np.random.default_rng(13)
+    t = np.concatenate([rng.uniform(0.0, 0.25, 200_000),
+                        10.0 ** rng.uniform(-9, np.log10(0.25), 200_000)]).astype(np.float32)
+    u = (np.float32(1.0) + t).astype(np.float32)
+    c = (t - (u - np.float32(1.0))).astype(np.float32)
+    t64, u64, c64 = t.astype(np.float64), u.astype(np.float64), c.astype(np.float64)
+    assert np.array_equal(u64 + c64, 1.0 + t64)          # c is the exact rounding error
+    approx = np.log(u64) + c64
+    exact = np.log1p(t64)
+    ok = exact > 0
+    rel = np.abs(approx[ok] - exact[ok]) / exact[ok]
+    assert rel.max() <= 1.2e-7
+    big = t64[ok] > 2.0 ** -16
+    assert rel[big].max() <= 1.01 * 2.0 ** -24
+    # near the worst case, t just above 2^-24, the error exceeds 2^-24 t
+    # (0.75 * 2^-23 t: the -t^2/2 of log1p cancels a quarter of it)
+    tw = np.float32(2.0 ** -24 * (1 + 2.0 ** -20))
+    uw = np.float32(np.float32(1.0) + tw)
+    cw = np.float64(np.float32(tw - (uw - np.float32(1.0))))
+    rw = abs(np.log(np.float64(uw)) + cw - np.log1p(np.float64(tw))) / np.log1p(np.float64(tw))
+    assert 1.4 * 2.0 ** -24 < rw < 2.0 ** -23
