@@ -41,6 +41,7 @@
 
 #include "api_internal.h"
 #include "sweep_bodies.h"
+#include "admission.h"
 #include "pool_allocator.h"
 
 using namespace grav;
@@ -366,30 +367,20 @@ void grav_server::run() {
     for (;;) {
         cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
         if (stop && queue.empty() && active.empty()) break;
-        // admission (see the policy at the top of this file)
-        bool inv_blocked = false;
-        for (auto it = queue.begin(); it != queue.end();) {
-            Request *q = *it;
-            const bool fwd = q->r.kind == GRAV_REQ_FORWARD;
-            std::vector<int> &slots = fwd ? free_fwd_slots : free_inv_slots;
-            if (slots.empty()) {
-                if (fwd) break;                 // forwards keep their order
-                inv_blocked = true;             // forwards behind may pass
-                ++it;
-                continue;
-            }
-            if (!fwd && inv_blocked) { ++it; continue; }
-            size_t off = 0;
-            if (!alloc->alloc(q->bytes, &off)) break;   // memory: strict arrival order
-            it = queue.erase(it);
-            q->off = off;
-            q->slot = slots.back();
-            slots.pop_back();
-            request_layout(*q, pool + off);
-            q->phase = Phase::Init;
-            q->t_admit = Clock::now();
-            active.push_back(q);
-        }
+        // admission (policy at the top of this file and in admission.h)
+        admission_pass(
+            queue, [](Request *q) { return q->r.kind == GRAV_REQ_FORWARD; },
+            [&](bool fwd) { return !(fwd ? free_fwd_slots : free_inv_slots).empty(); },
+            [&](Request *q) { return alloc->alloc(q->bytes, &q->off); },
+            [&](Request *q, bool fwd) {
+                std::vector<int> &slots = fwd ? free_fwd_slots : free_inv_slots;
+                q->slot = slots.back();
+                slots.pop_back();
+                request_layout(*q, pool + q->off);
+                q->phase = Phase::Init;
+                q->t_admit = Clock::now();
+                active.push_back(q);
+            });
         if (active.empty()) continue;   // head of queue cannot fit: nothing else can run
         std::vector<Request *> work = active;
         lk.unlock();
