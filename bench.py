@@ -348,6 +348,46 @@ def run_cg_full(args) -> int:
     return 0
 
 
+def run_profile_op(args) -> int:
+    """Only one operator at paper scale (178,797 obs x 3,307,500 prisms,
+    GRAV_MIXED), args.steps times after args.warmup untimed calls: the target
+    of the counter and kernel-trace runs of a single sweep."""
+    import torch
+    import paper_2602_03857_amd as g
+    p = workloads.paper_scale()
+    dev = torch.device("cuda", 0)
+    mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
+    obs = g.DeviceObs.from_survey(p.obs, dev)
+    m = torch.as_tensor(p.m, device=dev)
+    v = torch.as_tensor(p.probe_v, device=dev)
+    w = torch.as_tensor(p.wdepth, device=dev)
+    out_n = torch.empty(p.obs.n, dtype=torch.float64, device=dev)
+    out_m = torch.empty(p.mesh.ncells, dtype=torch.float64, device=dev)
+    ops = {
+        "forward": ("forward_mixed", lambda c: c.forward(mesh, obs, m, out_n, prec=g.GRAV_MIXED)),
+        "adjoint": ("adjoint_mixed", lambda c: c.adjoint(mesh, obs, v, out_m, prec=g.GRAV_MIXED)),
+        "dataspace": ("adjoint_mixed", lambda c: c.dataspace_apply(mesh, obs, w, 1e-12, v, out_n,
+                                                                   prec=g.GRAV_MIXED)),
+    }
+    kname, call = ops[args.profile_op]
+    with g.Context(0, validate=False) as ctx:
+        ctx.set_timing(True)
+        for _ in range(args.warmup):
+            call(ctx)
+        torch.cuda.synchronize()
+        ctx.reset_timing()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            call(ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        k_ms, k_n = ctx.kernel_time(kname)
+    print(json.dumps({"profile_op": args.profile_op, "steps": args.steps,
+                      "ms_per_call": 1e3 * dt / max(args.steps, 1), "kernel": kname,
+                      "kernel_ms_avg": k_ms / max(k_n, 1), "launches": k_n}), flush=True)
+    return 0
+
+
 def run_issue_probe(args) -> int:
     """Measure the issue rates behind the roofline's slot weights."""
     import torch  # noqa: F401
@@ -382,6 +422,8 @@ def main() -> int:
                     help="measure the instruction issue rates behind the roofline weights")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--profile-op", choices=("forward", "adjoint", "dataspace"),
+                    help="only time this operator at paper scale (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-baseline-requests", type=int, default=40)
     ap.add_argument("--serve-max-active", type=int, default=64)
@@ -400,6 +442,8 @@ def main() -> int:
         return run_cg_full(args)
     if args.issue_probe:
         return run_issue_probe(args)
+    if args.profile_op:
+        return run_profile_op(args)
     if args.copy_probe:
         import torch
         nbytes = args.copy_probe << 20
