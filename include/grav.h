@@ -287,7 +287,13 @@ typedef struct {
  *   FORWARD: m (M) -> d (n), d = G m.
  *   INVERT : d_obs (n), wdepth (M, > 0), lambda (< 0 = 1e-2 trace/n), cg
  *            options -> m_out (M) = C G^T y, y the CG solution of
- *            (G C G^T + lambda I) y = d_obs (reference model 0). */
+ *            (G C G^T + lambda I) y = d_obs (reference model 0).
+ * `stream` is the stream on which the caller produced the inputs (NULL = the
+ * null stream).  grav_server_submit makes the server wait for all work
+ * enqueued on it before the call, so inputs still being written
+ * asynchronously on that stream are complete before the server reads them;
+ * inputs written on any other stream must be complete before submit.
+ * Outputs are complete and visible once the request is reported done. */
 typedef struct {
     int32_t kind;            /* grav_req_kind */
     grav_mesh mesh;
@@ -299,6 +305,7 @@ typedef struct {
     double lambda;
     grav_cg_opts cg;
     double *m_out;
+    grav_stream stream;
 } grav_request;
 
 typedef struct {

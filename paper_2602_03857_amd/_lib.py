@@ -47,7 +47,8 @@ class CgInfo(ctypes.Structure):
 class GravRequest(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("mesh", CMesh), ("obs", CObs), ("m", ctypes.c_void_p),
                 ("d", ctypes.c_void_p), ("d_obs", ctypes.c_void_p), ("wdepth", ctypes.c_void_p),
-                ("lam", ctypes.c_double), ("cg", CgOpts), ("m_out", ctypes.c_void_p)]
+                ("lam", ctypes.c_double), ("cg", CgOpts), ("m_out", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
 
 
 class RequestInfo(ctypes.Structure):

@@ -203,6 +203,7 @@ struct grav_server {
     int max_active = 64;
     hipStream_t stream = nullptr;    // worker stream
     hipStream_t vstream = nullptr;   // submit-time validation stream
+    hipEvent_t vevent = nullptr;     // marks the end of a submitter's input work
     char *pool = nullptr;
     size_t pool_bytes = 0;
     PoolAllocator *alloc = nullptr;
@@ -389,6 +390,10 @@ void grav_server::run() {
         roctxRangePop();
         lk.lock();
         if (err) {
+            // kernels enqueued before the failure may still be writing the
+            // requests' outputs and pool ranges: let them finish before the
+            // requests are reported done and their memory is reused
+            (void)hipStreamSynchronize(stream);
             for (Request *q : work) {
                 q->status = GRAV_EDEVICE;
                 q->phase = Phase::Done;
@@ -453,6 +458,7 @@ extern "C" int grav_server_create(grav_server **out, const grav_server_opts *opt
     s->pool_bytes = opts.budget_bytes;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->vstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->vevent, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->pool), s->pool_bytes);
     const size_t nslots = 2 * (size_t)s->max_active;
     if (e == hipSuccess)
@@ -476,6 +482,7 @@ extern "C" int grav_server_create(grav_server **out, const grav_server_opts *opt
         if (s->ajobs_host) (void)hipHostFree(s->ajobs_host);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->vstream) (void)hipStreamDestroy(s->vstream);
+        if (s->vevent) (void)hipEventDestroy(s->vevent);
         grav_ctx_destroy(vctx);
         delete s;
         return oom ? GRAV_ENOMEM : GRAV_EDEVICE;
@@ -497,7 +504,12 @@ extern "C" int grav_server_submit(grav_server *s, const grav_request *req, uint6
     {
         std::lock_guard<std::mutex> vl(s->vmu);
         grav_ctx *v = s->vctx;
-        rc = check_geometry_host(v, &req->mesh, &req->obs);
+        // Order the validation (and with it every later read: validation
+        // waits for its stream) after the submitter's work on req->stream.
+        (void)hipSetDevice(s->device);
+        hipError_t ee = hipEventRecord(s->vevent, reinterpret_cast<hipStream_t>(req->stream));
+        if (ee == hipSuccess) ee = hipStreamWaitEvent(s->vstream, s->vevent, 0);
+        rc = ee == hipSuccess ? check_geometry_host(v, &req->mesh, &req->obs) : GRAV_EDEVICE;
         const Mesh g{req->mesh.nx, req->mesh.ny, req->mesh.nz, req->mesh.xn, req->mesh.yn, req->mesh.zn};
         const Obs o{req->obs.n, req->obs.x, req->obs.y, req->obs.z};
         if (!rc) {
@@ -611,6 +623,7 @@ extern "C" void grav_server_destroy(grav_server *s) {
     (void)hipHostFree(s->ajobs_host);
     (void)hipStreamDestroy(s->stream);
     (void)hipStreamDestroy(s->vstream);
+    (void)hipEventDestroy(s->vevent);
     grav_ctx_destroy(s->vctx);
     delete s->alloc;
     delete s;

@@ -51,6 +51,12 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
+    def _stream(self) -> int:
+        """torch's current stream on the server's device: the inputs of a
+        request are typically produced there, and submit orders the server's
+        reads after everything already enqueued on it."""
+        return torch.cuda.current_stream(self.device).cuda_stream
+
     def _submit(self, req: GravRequest, keep) -> int:
         t = ctypes.c_uint64()
         rc = lib.grav_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
@@ -63,7 +69,8 @@ class Server:
     def submit_forward(self, mesh: DeviceMesh, obs: DeviceObs, m, d) -> int:
         _check(m, torch.float64, mesh.ncells, "m", self.device)
         _check(d, torch.float64, obs.n, "d", self.device)
-        req = GravRequest(kind=REQ_FORWARD, mesh=mesh.c, obs=obs.c, m=m.data_ptr(), d=d.data_ptr())
+        req = GravRequest(kind=REQ_FORWARD, mesh=mesh.c, obs=obs.c, m=m.data_ptr(), d=d.data_ptr(),
+                          stream=self._stream())
         return self._submit(req, (mesh, obs, m, d))
 
     def submit_invert(self, mesh: DeviceMesh, obs: DeviceObs, d_obs, wdepth, m_out, lam=-1.0,
@@ -74,7 +81,7 @@ class Server:
         req = GravRequest(kind=REQ_INVERT, mesh=mesh.c, obs=obs.c, d_obs=d_obs.data_ptr(),
                           wdepth=wdepth.data_ptr(), lam=float(lam),
                           cg=CgOpts(float(tol), int(max_iter), int(fixed_iters), 0, 0, 0, 0, 0, None, None, None),
-                          m_out=m_out.data_ptr())
+                          m_out=m_out.data_ptr(), stream=self._stream())
         return self._submit(req, (mesh, obs, d_obs, wdepth, m_out))
 
     def poll(self, ticket: int):

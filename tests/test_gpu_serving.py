@@ -283,3 +283,29 @@ def test_largest_slot_count_with_many_small_requests(g):
     assert all(torch.equal(d, ref) for d in outs[::37])
     with pytest.raises(g.GravError):
         g.Server(0, max_active=257)
+
+
+def test_inputs_produced_asynchronously_on_the_current_stream(g):
+    """A request whose density is still being written on torch's current
+    stream when it is submitted: submit orders the server's reads after that
+    work, so the result equals the single-call forward of the final density."""
+    import torch
+    p = workloads.random_case(140, 24, 20, 9, 400, model="blocky", on_top=40)
+    mesh, obs = g.DeviceMesh.from_mesh(p.mesh), g.DeviceObs.from_survey(p.obs)
+    with g.Context(0) as ctx:
+        ref = to_np(ctx.forward(mesh, obs, _t(p.m), prec=g.GRAV_MIXED))
+    m_host = torch.as_tensor(p.m).pin_memory()
+    side = torch.cuda.Stream()
+    with g.Server(0, budget_bytes=1 << 28) as srv, torch.cuda.stream(side):
+        # a queue of device work ahead of the copy that fills m
+        a = torch.randn(2048, 2048, device="cuda")
+        for _ in range(24):
+            a = torch.tanh(a @ a * 1e-3)
+        m = torch.empty(p.mesh.ncells, dtype=torch.float64, device="cuda")
+        m.fill_(float("nan"))
+        m.copy_(m_host, non_blocking=True)
+        d = torch.empty(p.obs.n, dtype=torch.float64, device="cuda")
+        info = srv.wait(srv.submit_forward(mesh, obs, m, d))
+        assert info["status"] == g.GRAV_OK
+        side.synchronize()
+    assert np.array_equal(to_np(d), ref)
