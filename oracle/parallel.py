@@ -31,6 +31,11 @@ def _multi_rows(rows):
     return prism.forward_multi(s["mesh"], s["obs"], s["models"], rows=rows)
 
 
+def _adjoint_rows(rows):
+    s = _STATE
+    return prism.adjoint(s["mesh"], s["obs"].take(rows), s["v"][rows])[None, :]
+
+
 def _run(fn, rows, workers, **state):
     rows = np.asarray(rows)
     workers = max(1, min(int(workers), rows.size))
@@ -59,6 +64,16 @@ def weighted_row_sumsq(mesh, obs, cov, rows, workers=None):
     """``prism.weighted_row_sumsq`` split over processes."""
     return _run(_sumsq_rows, rows, workers or default_workers(), mesh=mesh, obs=obs,
                 cov=np.asarray(cov, dtype=np.float64))
+
+
+def adjoint(mesh, obs, v, rows=None, workers=None):
+    """``prism.adjoint`` over the observations ``rows`` (default all): each
+    process sums G^T v over its share of the observations, and the shares'
+    results are added (G^T v is linear in v)."""
+    rows = np.arange(obs.n) if rows is None else np.asarray(rows)
+    parts = _run(_adjoint_rows, rows, workers or default_workers(), mesh=mesh, obs=obs,
+                 v=np.asarray(v, dtype=np.float64))
+    return parts.sum(axis=0)
 
 
 def forward_multi_rows(mesh, obs, models, rows, workers=None):
