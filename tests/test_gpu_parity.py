@@ -2,8 +2,10 @@
 CPU oracle on the same seeded inputs.
 
 Tolerances: GRAV_FP64 to 1e-10 relative L2 (both are FP64; only summation
-order differs); GRAV_MIXED to 1e-5 relative L2 for gz (the accuracy target of
-the mixed path) and 1e-4 relative L2 for the recovered density."""
+order differs), except the plain FP64 adjoint on the full-size meshes, whose
+cap follows the rounding scale of its corner-term sums (_f64_corner_cap);
+GRAV_MIXED to 1e-5 relative L2 for gz (the accuracy target of the mixed path)
+and 1e-4 relative L2 for the recovered density."""
 import os
 
 import numpy as np
@@ -25,6 +27,20 @@ C_TERMS = 16.0
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+# The plain FP64 adjoint sums corner terms Psi(node - obs) of magnitude about
+# R ln R (Eq. 2) over the observations and then takes the 8-term vertex
+# alternation of Eq. 1, which cancels all but about (a/R)^3 / ln R of them for
+# a cell of size a at distance R.  Its rounding scale is therefore
+# eps64 * sum |corner terms|, not eps64 * |value|: at 100 x 100 x 50 cells (R/a
+# up to about 150) about 1e-9 of the value, at paper scale about 1e-8.  Its
+# relative L2 cap is the L2 form of the same C_TERMS * eps64 * sum |terms|
+# bound the entrywise check applies, never below TOL_F64.
+
+
+def _f64_corner_cap(ref, scale):
+    return max(TOL_F64, C_TERMS * 2.0 ** -53 * float(np.linalg.norm(scale) / np.linalg.norm(ref)))
+
+
 def _check_termwise(name, got, ref, scale, eps=EPS32, informative=True, rel_cap=TOL_MIXED):
     """|got - ref| <= C_TERMS * eps * scale elementwise (scale = sum of the
     magnitudes of the terms the GPU adds up, from the oracle).
@@ -36,8 +52,9 @@ def _check_termwise(name, got, ref, scale, eps=EPS32, informative=True, rel_cap=
     bound = C_TERMS * eps * scale
     ratio = np.abs(got - ref) / bound
     err = rel_l2(got, ref)
-    print(f"[parity] {name}: rel L2 = {err:.3e}, worst err / term bound = {ratio.max():.3f}, "
-          f"largest bound / |value| = {np.max(bound / np.abs(ref)):.2e}", flush=True)
+    print(f"[parity] {name}: rel L2 = {err:.3e} (cap {rel_cap:.1e}), worst err / term bound = "
+          f"{ratio.max():.3f}, largest bound / |value| = {np.max(bound / np.abs(ref)):.2e}",
+          flush=True)
     assert np.all(ratio <= 1.0)
     if informative:
         assert np.all(bound < np.abs(ref)), "term bound does not exclude a zero output"
@@ -470,7 +487,8 @@ def test_ellipsoids_100x100x50_forward_adjoint_sampled(g, ctx):
         if prec_name == "GRAV_FP64":
             # corner terms ~R ln R, each within a few ulp: C_TERMS * eps64 * sum |terms|
             _check_termwise(f"ellipsoids_100x100x50 adjoint {prec_name} (64 cells)", got, ref,
-                            gold["gtv_abs_corners"], eps=2.0 ** -53, rel_cap=TOL_F64)
+                            gold["gtv_abs_corners"], eps=2.0 ** -53,
+                            rel_cap=_f64_corner_cap(ref, gold["gtv_abs_corners"]))
         else:
             _check_termwise(f"ellipsoids_100x100x50 adjoint {prec_name} (64 cells)", got, ref,
                             gold["gtv_abs"])
@@ -522,7 +540,8 @@ def test_paper_scale_adjoint_fp64_sampled_cells(g, ctx):
     mesh, obs = _dev(g, p)
     gt = to_np(ctx.adjoint(mesh, obs, _t(np.abs(p.probe_v)), prec=g.GRAV_FP64))
     _check_termwise("paper_scale adjoint GRAV_FP64 (48 cells)", gt[gold["cells"]], gold["gtv"],
-                    gold["gtv_abs_corners"], eps=2.0 ** -53, rel_cap=TOL_F64)
+                    gold["gtv_abs_corners"], eps=2.0 ** -53,
+                    rel_cap=_f64_corner_cap(gold["gtv"], gold["gtv_abs_corners"]))
 
 
 # ------------------------------------------------------------------ multi-model
