@@ -13,7 +13,9 @@ Printed (rank 0, one JSON line): the contract fields plus
   roofline      - the forward sweep kernel against the VALU issue limit,
   cpu_baseline  - the FP64 oracle on a bounded sample of rows, on host cores,
   extras        - adjoint sweep, data-space apply, plain-FP64 speed-up, CG
-                  iterations/s (a few iterations), error vs the oracle rows.
+                  iterations/s (a few iterations), error vs the oracle rows,
+                  and (serving) CG solve p50/p99 latency over the first 60
+                  requests of the serving stream with an FP64 FIFO baseline.
 """
 from __future__ import annotations
 
@@ -144,7 +146,8 @@ def ellipsoids_extras(g, torch, dev):
     mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
     obs = g.DeviceObs.from_survey(p.obs, dev)
     m = torch.as_tensor(p.m, device=dev)
-    v = torch.as_tensor(p.probe_v, device=dev)
+    # the stored G^T v cells are for the sign-definite probe |probe_v|
+    v = torch.as_tensor(np.abs(p.probe_v), device=dev)
     gold_path = os.path.join(ROOT, "tests", "golden", "ellipsoids_100x100x50_rows.npz")
     gold = np.load(gold_path) if os.path.exists(gold_path) else None
     ctx = g.Context(0, validate=False)
@@ -203,22 +206,24 @@ def _percentiles(lat):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def run_serve(args) -> int:
-    """Replay the serving stream (Poisson arrivals) open-loop on wall-clock time
-    through the continuous-batching server, then the same arrivals through a
-    one-at-a-time FIFO of the plain FP64 single-call path."""
-    import torch
-    import paper_2602_03857_amd as g
-    dev = torch.device("cuda", 0)
-    reqs = workloads.serving_stream()[: args.serve_requests]
+def serve_replay(g, torch, dev, n_requests, max_active, budget_gb, fifo_requests,
+                 fifo_budget_s=None, progress=True):
+    """Replay the first n_requests of the serving stream (Poisson arrivals)
+    open-loop on wall-clock time through the continuous-batching server, then
+    the first fifo_requests of the same arrivals through a one-at-a-time FIFO
+    of the plain FP64 single-call path (stopped after fifo_budget_s seconds of
+    wall time if given; the requests it finished are reported)."""
+    from paper_2602_03857_amd import GRAV_ENOCONV
+    reqs = workloads.serving_stream()[:n_requests]
     ctx = g.Context(0, validate=False)
     items = _serve_inputs(g, torch, dev, reqs, ctx)
     pairs = [it["n"] * it["M"] for it in items]
-    print(f"[serve] {len(items)} requests staged on the device", file=sys.stderr, flush=True)
+    if progress:
+        print(f"[serve] {len(items)} requests staged on the device", file=sys.stderr, flush=True)
 
     # continuous batching
-    lat, iters = [None] * len(items), {}
-    srv = g.Server(0, max_active=args.serve_max_active, budget_bytes=args.serve_budget_gb << 30)
+    lat, iters, noconv = [None] * len(items), {}, 0
+    srv = g.Server(0, max_active=max_active, budget_bytes=budget_gb << 30)
     t0 = time.perf_counter()
     pending, nxt = {}, 0
     while nxt < len(items) or pending:
@@ -241,8 +246,9 @@ def run_serve(args) -> int:
                 lat[k] = time.perf_counter() - t0 - it["t"]
                 if it["kind"] != "forward":
                     iters[k] = info["iters"]
+                    noconv += int(info["status"] == GRAV_ENOCONV)
                 ndone = sum(x is not None for x in lat)
-                if ndone % 20 == 0:
+                if progress and ndone % 20 == 0:
                     print(f"[serve] {ndone} done", file=sys.stderr, flush=True)
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
@@ -253,9 +259,14 @@ def run_serve(args) -> int:
     # segment pairs swept: forward = 1 sweep; inversion = trace (2) + 2 per CG iteration + final adjoint
     served_pairs = sum(pairs[i] if it["kind"] == "forward" else pairs[i] * (2 * iters[i] + 3)
                        for i, it in enumerate(items))
-    res = {"requests": len(items), "p50_s": p50, "p99_s": p99, "inversion_p50_s": i50,
+    res = {"workload": f"serving_stream: first {len(items)} of 200 requests (Poisson arrivals, "
+                       "mean gap 0.5 s; forward or inversion, N 1k-40k, 50k-800k cells; "
+                       "CG to 1e-6, at most 200 iterations), GRAV_MIXED",
+           "requests": len(items), "p50_s": p50, "p99_s": p99, "inversion_p50_s": i50,
+           "inversion_p99_s": i99, "inversions": len(inv),
+           "inversions_at_iteration_cap": noconv, "wall_s": wall,
+           "requests_per_s": len(items) / wall,
            "served_segment_pairs_per_s": served_pairs / wall,
-           "inversion_p99_s": i99, "wall_s": wall, "requests_per_s": len(items) / wall,
            "pairs_per_s_forward_requests": sum(pairs[i] for i, it in enumerate(items)
                                                if it["kind"] == "forward") / wall,
            "mean_cg_iters": float(np.mean(list(iters.values()))) if iters else 0}
@@ -271,13 +282,15 @@ def run_serve(args) -> int:
                                          "median": float(np.median(errs))}
 
     # one-at-a-time FIFO of the plain FP64 path on the same arrivals
-    nb = min(args.serve_baseline_requests, len(items))
+    nb = min(fifo_requests, len(items))
     if nb > 0:
         ctx64 = g.Context(0, validate=False)
         lat_b = []
         t0 = time.perf_counter()
         for it in items[:nb]:
             now = time.perf_counter() - t0
+            if fifo_budget_s is not None and now > fifo_budget_s:
+                break
             if now < it["t"]:
                 time.sleep(it["t"] - now)
             if it["kind"] == "forward":
@@ -288,17 +301,30 @@ def run_serve(args) -> int:
                              max_iter=it["max_iter"], m_out=it["m_out"], prec=g.GRAV_FP64)
                 _ = it["m_out"].cpu()
             lat_b.append(time.perf_counter() - t0 - it["t"])
-            print(f"[serve] fp64 fifo {len(lat_b)}/{nb}", file=sys.stderr, flush=True)
+            if progress:
+                print(f"[serve] fp64 fifo {len(lat_b)}/{nb}", file=sys.stderr, flush=True)
+        nd = len(lat_b)
         b50, b99 = _percentiles(lat_b)
-        s50, s99 = _percentiles(lat[:nb])
-        res["fp64_fifo_baseline"] = {"requests": nb, "p50_s": b50, "p99_s": b99,
+        s50, s99 = _percentiles(lat[:nd])
+        res["fp64_fifo_baseline"] = {"requests": nd, "p50_s": b50, "p99_s": b99,
                                      "wall_s": time.perf_counter() - t0,
                                      "batched_same_requests_p50_s": s50,
                                      "batched_same_requests_p99_s": s99}
         ctx64.close()
+    ctx.close()
+    return res
+
+
+def run_serve(args) -> int:
+    """The whole serving stream (--serve-requests of 200) through the server,
+    and --serve-baseline-requests of it through the FP64 FIFO."""
+    import torch
+    import paper_2602_03857_amd as g
+    dev = torch.device("cuda", 0)
+    res = serve_replay(g, torch, dev, args.serve_requests, args.serve_max_active,
+                       args.serve_budget_gb, args.serve_baseline_requests)
     print(json.dumps({"metric": "CG solve p50/p99 latency, serving stream", "serving": res}),
           flush=True)
-    ctx.close()
     return 0
 
 
@@ -344,6 +370,67 @@ def run_cg_full(args) -> int:
            "adjoint_kernel_ms_avg": a_ms / max(a_n, 1), "relres": info["relres"],
            "lambda": info["lambda_used"], "data_misfit_rel": misfit, "noise_rel": noise,
            "data": "synthetic (seeded paper-scale survey, model and noise)"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_cg_compare(args) -> int:
+    """Paper-scale solver evidence on the configured inversion (178,797 obs x
+    3,307,500 prisms, 2 % noise, lambda = 1e-2 trace / N, plain CG from 0):
+    (1) the relative-residual history of the first --cg-compare-iters
+    iterations in GRAV_MIXED and in GRAV_FP64, entry by entry, and the two
+    recovered densities after them; (2) plain against Jacobi-preconditioned
+    CG (GRAV_MIXED) over --cg-jacobi-iters iterations: the iteration at which
+    each first reaches a relative residual of 0.5, 0.3, 0.2 and 0.15."""
+    import torch
+    import paper_2602_03857_amd as g
+    p = workloads.paper_scale()
+    dev = torch.device("cuda", 0)
+    mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
+    obs = g.DeviceObs.from_survey(p.obs, dev)
+    m_true = torch.as_tensor(p.m, device=dev)
+    w = torch.as_tensor(p.wdepth, device=dev)
+    out = {"metric": "paper-scale CG: mixed vs FP64 residual histories; plain vs Jacobi",
+           "data": "synthetic (seeded paper-scale survey, model and noise)"}
+    with g.Context(0, validate=True) as ctx:
+        d = ctx.forward(mesh, obs, m_true, prec=g.GRAV_MIXED)
+        draws = torch.as_tensor(p.noise_draws, device=dev)
+        d_obs = d + p.noise_level * torch.sqrt(torch.mean(d * d)) * draws
+        torch.cuda.synchronize()
+        k = args.cg_compare_iters
+        hist, dens = {}, {}
+        for prec, tag in ((g.GRAV_MIXED, "mixed"), (g.GRAV_FP64, "fp64")):
+            t0 = time.perf_counter()
+            m, _, info = ctx.invert(mesh, obs, d_obs, w, lam=-1.0, tol=0.0, max_iter=k,
+                                    history_cap=k, prec=prec)
+            torch.cuda.synchronize()
+            hist[tag] = info["history"]
+            dens[tag] = m.clone()
+            out[f"{tag}_solve_s"] = time.perf_counter() - t0
+            out[f"{tag}_lambda"] = info["lambda_used"]
+            print(f"[cg-compare] {tag}: {k} iterations in {out[f'{tag}_solve_s']:.1f} s",
+                  file=sys.stderr, flush=True)
+        out["history_mixed"] = hist["mixed"]
+        out["history_fp64"] = hist["fp64"]
+        out["history_max_rel_diff"] = float(max(abs(a - b) / b for a, b in
+                                                zip(hist["mixed"], hist["fp64"])))
+        out["lambda_rel_diff"] = abs(out["mixed_lambda"] - out["fp64_lambda"]) / out["fp64_lambda"]
+        out["density_rel_l2_mixed_vs_fp64"] = float(
+            torch.linalg.norm(dens["mixed"] - dens["fp64"]) / torch.linalg.norm(dens["fp64"]))
+        j = args.cg_jacobi_iters
+        if j > 0:
+            for pc, tag in ((0, "plain"), (1, "jacobi")):
+                t0 = time.perf_counter()
+                _, _, info = ctx.invert(mesh, obs, d_obs, w, lam=-1.0, tol=0.0, max_iter=j,
+                                        history_cap=j, precond=pc, prec=g.GRAV_MIXED)
+                torch.cuda.synchronize()
+                h = info["history"]
+                out[f"{tag}_history"] = h
+                out[f"{tag}_solve_s"] = time.perf_counter() - t0
+                out[f"{tag}_iters_to"] = {str(th): next((i + 1 for i, r in enumerate(h) if r <= th),
+                                                        None) for th in (0.5, 0.3, 0.2, 0.15)}
+                print(f"[cg-compare] {tag}: {j} iterations in {out[f'{tag}_solve_s']:.1f} s",
+                      file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -418,12 +505,20 @@ def main() -> int:
     ap.add_argument("--serve", action="store_true", help="replay the serving stream instead")
     ap.add_argument("--cg-full", action="store_true",
                     help="time the paper-scale 50-iteration CG solve instead")
+    ap.add_argument("--cg-compare", action="store_true",
+                    help="paper-scale CG: mixed vs FP64 histories, plain vs Jacobi")
+    ap.add_argument("--cg-compare-iters", type=int, default=6)
+    ap.add_argument("--cg-jacobi-iters", type=int, default=50)
     ap.add_argument("--issue-probe", action="store_true",
                     help="measure the instruction issue rates behind the roofline weights")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--profile-op", choices=("forward", "adjoint", "dataspace"),
                     help="only time this operator at paper scale (profiling runs)")
+    ap.add_argument("--serve-extras-requests", type=int, default=60,
+                    help="requests of the serving stream replayed in the default run (0 = none)")
+    ap.add_argument("--serve-extras-fifo", type=int, default=10,
+                    help="of those, requests replayed through the FP64 FIFO (at most 30 s)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-baseline-requests", type=int, default=40)
     ap.add_argument("--serve-max-active", type=int, default=64)
@@ -440,6 +535,8 @@ def main() -> int:
         return run_serve(args)
     if args.cg_full:
         return run_cg_full(args)
+    if args.cg_compare:
+        return run_cg_compare(args)
     if args.issue_probe:
         return run_issue_probe(args)
     if args.profile_op:
@@ -582,6 +679,11 @@ def main() -> int:
         extras.update(multi_model_extras(g, torch, dev))
     if not args.no_extras:
         extras.update(ellipsoids_extras(g, torch, dev))
+    if not args.no_extras and args.serve_extras_requests > 0:
+        # the metric's second half: CG solve latency under the serving stream
+        extras["serving"] = serve_replay(g, torch, dev, args.serve_extras_requests,
+                                         args.serve_max_active, args.serve_budget_gb,
+                                         args.serve_extras_fifo, fifo_budget_s=30.0)
 
     out = {
         "metric": "prism-obs pairs/s for G.m at 3.3M x 178,797",

@@ -106,7 +106,7 @@ typedef struct grav_ctx grav_ctx;
 /* Operation codes for grav_workspace_bytes(). */
 typedef enum {
     GRAV_OP_FORWARD = 0, GRAV_OP_ADJOINT = 1, GRAV_OP_DATASPACE = 2, GRAV_OP_TRACE = 3,
-    GRAV_OP_INVERT = 4, GRAV_OP_FORWARD_MULTI = 5, GRAV_OP_TREND = 6
+    GRAV_OP_INVERT = 4, GRAV_OP_FORWARD_MULTI = 5, GRAV_OP_TREND = 6, GRAV_OP_SECTIONS = 7
 } grav_op;
 
 /* Fill `opts` with the defaults (device 0, validate 1, 4 GiB workspace). */
@@ -155,7 +155,10 @@ int grav_dataspace_apply(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *o
                          grav_prec prec, grav_stream stream);
 
 /* trace(G C G^T) = sum_o sum_k C_k G_ok^2 with C = diag(wdepth^-2), written to
- * *trace (HOST pointer; the call waits for the result).  Optional `diag`
+ * *trace (HOST pointer; the call waits for the result).  It sets the scale of
+ * the data-space covariance W_d = delta I of Section 2.2 (a diagonal term with
+ * one uniform value, which the paper does not give): grav_invert's
+ * lambda < 0 rule is delta = 1e-2 trace / n.  Optional `diag`
  * (device, n doubles, may be NULL) receives the per-observation terms
  * sum_k C_k G_ok^2, i.e. the diagonal of G C G^T.  prec : GRAV_MIXED or GRAV_FP64. */
 int grav_trace(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const double *wdepth,
@@ -226,8 +229,8 @@ int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs, const
                 grav_prec prec, grav_stream stream);
 
 /* Regional-residual separation (the second-degree trend-surface removal of
- * the field workflow, Section 3.2; one surface over the whole domain also
- * joins sections inverted separately, Section 4.4): least-squares fit
+ * the field workflow, Section 2.2; one surface over the whole domain also
+ * joins sections inverted separately, Section 4.5): least-squares fit
  *   T(x, y) = sum_j coef[j] phi_j(u, w),  u = (x - x0) / L,  w = (y - y0) / L,
  *   phi = (1, u, w, u^2, u w, w^2) for degree 2, (1, u, w) for degree 1,
  * (x0, y0) the centre of the points' bounding box and L half its larger side
@@ -245,6 +248,53 @@ int grav_trend_surface(grav_ctx *ctx, const double *x, const double *y, const do
                        int64_t n, int32_t degree, double *coef, double *frame, double *resid,
                        double *trend, grav_stream stream);
 
+/* Regional inversion by adjoining sections (Section 4.5, with the trend
+ * separation of Section 2.2).  A regional problem too large to invert at once
+ * is divided into sections that adjoin along y; each is inverted on its own
+ * (grav_invert's data-space CG, Eq. 10-11, reference model 0) from its own
+ * stations; the section models are placed into the regional mesh; then one
+ * trend surface per layer, fitted across the complete domain, is removed from
+ * the combined model to even out the steps the separate inversions leave at
+ * the section boundaries.
+ *   Section s spans mesh node rows ysplit[s] .. ysplit[s+1] of y (cells
+ *   ysplit[s] .. ysplit[s+1]-1) and owns the stations with
+ *   yn[ysplit[s]] <= y < yn[ysplit[s+1]]; stations below yn[ysplit[1]] belong
+ *   to section 0 and those at or above yn[ysplit[nsec-1]] to the last one.
+ *   data_degree (0 = none, 1, 2): the data minus its least-squares trend
+ *   surface (grav_trend_surface) is inverted, the surface fitted per section
+ *   (GRAV_TREND_SECTION: each section processed like a survey of its own) or
+ *   once over all stations (GRAV_TREND_DOMAIN).
+ *   model_degree (0, 1, 2): per layer k, the surface fitted to the combined
+ *   model's layer values at the cell centres (x, y) is subtracted.
+ *   lambda < 0: each section uses 1e-2 trace(G_s C_s G_s^T) / n_s. */
+typedef enum { GRAV_TREND_SECTION = 0, GRAV_TREND_DOMAIN = 1 } grav_trend_scope;
+
+typedef struct {
+    int32_t nsec;            /* 1 .. 64 sections */
+    const int32_t *ysplit;   /* HOST, nsec + 1 node indices: 0 = ysplit[0] < ... < ysplit[nsec] = ny */
+    int32_t data_degree;     /* 0, 1 or 2 */
+    int32_t data_scope;      /* grav_trend_scope */
+    int32_t model_degree;    /* 0, 1 or 2 */
+} grav_section_opts;
+
+/*   d_obs : n doubles; wdepth : M doubles (> 0); cg : as for grav_invert,
+ *   without y0, y_out or history (they must be NULL / 0);
+ *   m_out : M doubles (output): the combined model;
+ *   m_detrended : M doubles (output) or NULL: m_out minus its per-layer trend
+ *   (a copy of m_out when model_degree = 0); may not alias m_out;
+ *   info : HOST array of nsec entries or NULL: each section's CG summary.
+ *   The call waits for completion.
+ * Returns GRAV_OK, GRAV_ENOCONV (a section reached its iteration cap; all
+ * outputs valid), or an error: GRAV_EINVAL also for a section without
+ * stations, fewer stations (or horizontal cells) than a trend surface needs,
+ * or points that do not determine it; GRAV_ENOMEM below
+ * grav_workspace_bytes(.., GRAV_OP_SECTIONS, ..), which bounds any split. */
+int grav_invert_sections(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                         const double *d_obs, const double *wdepth, double lambda,
+                         const grav_cg_opts *cg, const grav_section_opts *sec, double *m_out,
+                         double *m_detrended, grav_cg_info *info, grav_prec prec,
+                         grav_stream stream);
+
 /* Multi-model forward D = G [m_1 ... m_K] (Eq. 6 for a block of models, a
  * dense contraction over prisms).
  *   models : M x K floats, model index fastest (models[k*K + j]);
@@ -253,6 +303,7 @@ int grav_trend_surface(grav_ctx *ctx, const double *x, const double *y, const do
 int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
                        const float *models, int32_t K, float *D, grav_prec prec,
                        grav_stream stream);
+
 
 
 /* ---------------------------------------------------------------------------

@@ -1,7 +1,7 @@
 """FP64 CPU oracle for the regional-residual separation: least-squares
 polynomial trend surface in the horizontal coordinates (the second-degree
-trend removal of the field workflow, Section 3.2; one surface over the whole
-domain joins separately inverted sections, Section 4.4).
+trend removal of the field workflow, Section 2.2; one surface over the whole
+domain joins separately inverted sections, Section 4.5).
 
 TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the CPU
 baseline of the benchmark, never by the product path.

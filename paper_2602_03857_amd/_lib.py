@@ -8,7 +8,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrav.so"
 
 GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV, GRAV_EBUSY, GRAV_ECANCELED = range(7)
 GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU = range(4)
-OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND = range(7)
+OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND, OP_SECTIONS = range(8)
+GRAV_TREND_SECTION, GRAV_TREND_DOMAIN = range(2)
 GRAV_GAMMA = 6.674e-11
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -42,6 +43,12 @@ class CgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double),
                 ("lambda_used", ctypes.c_double), ("trace", ctypes.c_double),
                 ("cycles", ctypes.c_int32), ("halvings", ctypes.c_int32)]
+
+
+class SectionOpts(ctypes.Structure):
+    _fields_ = [("nsec", ctypes.c_int32), ("ysplit", ctypes.POINTER(ctypes.c_int32)),
+                ("data_degree", ctypes.c_int32), ("data_scope", ctypes.c_int32),
+                ("model_degree", ctypes.c_int32)]
 
 
 class GravRequest(ctypes.Structure):
@@ -98,6 +105,9 @@ def _load():
                                        P(CgInfo), ctypes.c_int, vp]),
         "grav_forward_multi": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, i32, vp, ctypes.c_int,
                                               vp]),
+        "grav_invert_sections": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, vp, dbl, P(CgOpts),
+                                                P(SectionOpts), vp, vp, P(CgInfo), ctypes.c_int,
+                                                vp]),
         "grav_server_create": (ctypes.c_int, [P(vp), P(ServerOpts)]),
         "grav_server_submit": (ctypes.c_int, [vp, P(GravRequest), P(ctypes.c_uint64)]),
         "grav_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, P(i32), P(RequestInfo)]),
@@ -122,7 +132,7 @@ EXPORTED = [
     "grav_ctx_opts_default", "grav_ctx_create", "grav_ctx_destroy", "grav_last_error",
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
     "grav_trend_surface",
-    "grav_invert", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
+    "grav_invert", "grav_invert_sections", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
     "grav_reset_timing", "grav_issue_rates", "grav_server_create", "grav_server_submit", "grav_server_poll",
     "grav_server_wait", "grav_server_cancel", "grav_server_destroy",
 ]

@@ -10,8 +10,9 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (lib, GravError, CMesh, CObs, CtxOpts, CgOpts, CgInfo, GRAV_OK, GRAV_ENOCONV,
-                   GRAV_MIXED, GRAV_MIXED_BF16X3, OP_FORWARD)
+from ._lib import (lib, GravError, CMesh, CObs, CtxOpts, CgOpts, CgInfo, SectionOpts, GRAV_OK,
+                   GRAV_ENOCONV, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_TREND_SECTION,
+                   GRAV_TREND_DOMAIN, OP_FORWARD)
 
 
 def _device_f64(a, device) -> torch.Tensor:
@@ -78,6 +79,7 @@ class DeviceObs:
 
 def workspace_bytes(nx, ny, nz, n, op=OP_FORWARD, prec=GRAV_MIXED, K=0) -> int:
     return int(lib.grav_workspace_bytes(nx, ny, nz, n, op, prec, K))
+
 
 
 class Context:
@@ -262,6 +264,43 @@ class Context:
                                    history=(list(hist[:min(info.iters, history_cap)])
                                             if history_cap > 0 and not fixed_iters else None),
                                    converged=(rc == GRAV_OK))
+
+    def invert_sections(self, mesh, obs, d_obs, wdepth, ysplit, data_degree=2,
+                        data_scope="section", model_degree=2, lam=-1.0, tol=1e-6, max_iter=200,
+                        fixed_iters=0, precond=0, restart=0, max_cycles=30, max_halvings=5,
+                        m_out=None, m_detrended=None, detrend=True, prec=GRAV_MIXED,
+                        stream=None):
+        """Regional inversion by adjoining sections along y (split at the mesh
+        node rows `ysplit`, 0 ... ny), each inverted on its own, combined, and
+        (detrend) a per-layer trend surface of `model_degree` removed.
+        data_scope: "section" or "domain".  Returns (m_out, m_detrended or
+        None, list of per-section info dicts)."""
+        _check(d_obs, torch.float64, obs.n, "d_obs", self.device)
+        _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
+        if m_out is None:
+            m_out = torch.empty(mesh.ncells, dtype=torch.float64, device=self.device)
+        _check(m_out, torch.float64, mesh.ncells, "m_out", self.device)
+        if m_detrended is None and detrend:
+            m_detrended = torch.empty(mesh.ncells, dtype=torch.float64, device=self.device)
+        if m_detrended is not None:
+            _check(m_detrended, torch.float64, mesh.ncells, "m_detrended", self.device)
+        scope = {"section": GRAV_TREND_SECTION, "domain": GRAV_TREND_DOMAIN}[data_scope]
+        nsec = len(ysplit) - 1
+        split = (ctypes.c_int32 * len(ysplit))(*[int(j) for j in ysplit])
+        so = SectionOpts(nsec, ctypes.cast(split, ctypes.POINTER(ctypes.c_int32)), int(data_degree),
+                         scope, int(model_degree))
+        cg = CgOpts(float(tol), int(max_iter), int(fixed_iters), int(precond), int(restart),
+                    int(max_cycles), int(max_halvings), 0, None, None, None)
+        infos = (CgInfo * max(nsec, 1))()
+        rc = lib.grav_invert_sections(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
+                                      d_obs.data_ptr(), wdepth.data_ptr(), float(lam),
+                                      ctypes.byref(cg), ctypes.byref(so), m_out.data_ptr(),
+                                      m_detrended.data_ptr() if m_detrended is not None else None,
+                                      infos, prec, self._stream(stream))
+        self._rc(rc, allow_noconv=True)
+        return m_out, m_detrended, [dict(iters=i.iters, relres=i.relres, lambda_used=i.lambda_used,
+                                         trace=i.trace, cycles=i.cycles, halvings=i.halvings)
+                                    for i in infos[:nsec]]
 
     def forward_multi(self, mesh, obs, models, D=None, prec=GRAV_MIXED_BF16X3, stream=None):
         """D = G M for models (M, K) float32 (model index fastest); returns (n, K) float32."""

@@ -33,8 +33,9 @@ int hip_fail(grav_ctx *ctx, hipError_t e, const char *where) {
 
 Arena ctx_arena(grav_ctx *ctx) {
     Arena a;
-    a.base = ctx->ws + kReserveBytes;
-    a.size = ctx->ws_bytes > kReserveBytes ? ctx->ws_bytes - kReserveBytes : 0;
+    const size_t head = kReserveBytes + ctx->arena_skip;
+    a.base = ctx->ws + head;
+    a.size = ctx->ws_bytes > head ? ctx->ws_bytes - head : 0;
     return a;
 }
 
@@ -274,6 +275,9 @@ extern "C" uint64_t grav_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int
                                          grav_prec prec, int32_t K) {
     if (op == GRAV_OP_TREND) return grav::trend_workspace_need();
     if (nx <= 0 || ny <= 0 || nz <= 0 || n <= 0) return 0;
+    if (op == GRAV_OP_SECTIONS)
+        return grav::sections_workspace_need(grav::Mesh{nx, ny, nz, nullptr, nullptr, nullptr}, n,
+                                             prec);
     return grav::workspace_need(nx, ny, nz, n, op, prec, K);
 }
 
@@ -386,6 +390,60 @@ extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs 
     if (rc) return rc;
     if (!d_obs || !wdepth || !cg || !m_out) return fail(ctx, GRAV_EINVAL, "d_obs, wdepth, cg or m_out is NULL");
     if (!std::isfinite(lambda)) return fail(ctx, GRAV_EINVAL, "lambda must be finite");
+    rc = check_cg_opts(ctx, cg);
+    if (rc) return rc;
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st,
+                            {ArrayCheck{wdepth, g.ncells(), true}, ArrayCheck{d_obs, o.n, false},
+                             ArrayCheck{m_ref, g.ncells(), false}, ArrayCheck{cg->y0, o.n, false}});
+    if (rc) return rc;
+    return grav::run_invert(ctx, g, o, d_obs, wdepth, lambda, m_ref, *cg, m_out, d_pred, info, prec, st);
+}
+
+extern "C" int grav_invert_sections(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
+                                    const double *d_obs, const double *wdepth, double lambda,
+                                    const grav_cg_opts *cg, const grav_section_opts *sec,
+                                    double *m_out, double *m_detrended, grav_cg_info *info,
+                                    grav_prec prec, grav_stream stream) {
+    ENTER(ctx);
+    int rc = check_geometry_host(ctx, mesh, obs);
+    if (rc) return rc;
+    if (!d_obs || !wdepth || !cg || !sec || !m_out)
+        return fail(ctx, GRAV_EINVAL, "d_obs, wdepth, cg, sec or m_out is NULL");
+    if (m_detrended == m_out) return fail(ctx, GRAV_EINVAL, "m_detrended may not alias m_out");
+    if (!std::isfinite(lambda)) return fail(ctx, GRAV_EINVAL, "lambda must be finite");
+    rc = check_cg_opts(ctx, cg);
+    if (rc) return rc;
+    if (cg->y0 || cg->y_out || cg->history_cap != 0)
+        return fail(ctx, GRAV_EINVAL, "section inversions take no y0, y_out or history");
+    if (sec->nsec < 1 || sec->nsec > kMaxSections || !sec->ysplit)
+        return fail(ctx, GRAV_EINVAL, "nsec must be 1..64 with a ysplit array");
+    if (sec->ysplit[0] != 0 || sec->ysplit[sec->nsec] != mesh->ny)
+        return fail(ctx, GRAV_EINVAL, "ysplit must run from 0 to ny");
+    for (int s = 0; s < sec->nsec; ++s)
+        if (sec->ysplit[s + 1] <= sec->ysplit[s])
+            return fail(ctx, GRAV_EINVAL, "ysplit must be strictly increasing");
+    if (sec->data_degree < 0 || sec->data_degree > 2 || sec->model_degree < 0 || sec->model_degree > 2)
+        return fail(ctx, GRAV_EINVAL, "trend degrees must be 0, 1 or 2");
+    if (sec->data_scope != GRAV_TREND_SECTION && sec->data_scope != GRAV_TREND_DOMAIN)
+        return fail(ctx, GRAV_EINVAL, "data_scope must be GRAV_TREND_SECTION or GRAV_TREND_DOMAIN");
+    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
+    const Mesh g = to_mesh(mesh);
+    const Obs o = to_obs(obs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    rc = validate_on_device(ctx, g, o, st,
+                            {ArrayCheck{wdepth, g.ncells(), true}, ArrayCheck{d_obs, o.n, false}});
+    if (rc) return rc;
+    return grav::run_sections(ctx, g, o, d_obs, wdepth, lambda, *cg, *sec, m_out, m_detrended,
+                              info, prec, st);
+}
+
+namespace grav {
+
+int check_cg_opts(grav_ctx *ctx, const grav_cg_opts *cg) {
     if (cg->restart < 0) return fail(ctx, GRAV_EINVAL, "restart must be >= 0");
     if (cg->history_cap < 0 || (cg->history_cap > 0 && !cg->history))
         return fail(ctx, GRAV_EINVAL, "history_cap must be >= 0, with a history array when > 0");
@@ -399,16 +457,10 @@ extern "C" int grav_invert(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs 
     }
     if (cg->precond != 0 && cg->precond != 1)
         return fail(ctx, GRAV_EINVAL, "precond must be 0 (none) or 1 (Jacobi)");
-    if (prec != GRAV_FP64 && prec != GRAV_MIXED) return fail(ctx, GRAV_EINVAL, "precision must be GRAV_FP64 or GRAV_MIXED");
-    const Mesh g = to_mesh(mesh);
-    const Obs o = to_obs(obs);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    rc = validate_on_device(ctx, g, o, st,
-                            {ArrayCheck{wdepth, g.ncells(), true}, ArrayCheck{d_obs, o.n, false},
-                             ArrayCheck{m_ref, g.ncells(), false}, ArrayCheck{cg->y0, o.n, false}});
-    if (rc) return rc;
-    return grav::run_invert(ctx, g, o, d_obs, wdepth, lambda, m_ref, *cg, m_out, d_pred, info, prec, st);
+    return GRAV_OK;
 }
+
+}  // namespace grav
 
 // ---------------------------------------------------------------- timing
 

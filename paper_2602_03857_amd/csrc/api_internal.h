@@ -20,6 +20,7 @@ struct grav_ctx {
     int *h_flags = nullptr;
     double *h_scal = nullptr;
     std::string err;
+    size_t arena_skip = 0;  // bytes at the arena's head held by an enclosing workflow
     bool timing = false;    // record events around sweep launches
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::map<std::string, std::pair<double, int64_t>> totals;
@@ -64,6 +65,13 @@ uint64_t trend_workspace_need();
 int op_issue_rates(grav_ctx *ctx, double *rates, hipStream_t st);
 int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
              double *trace, double *diag, grav_prec prec, hipStream_t st);
+constexpr int kMaxSections = 64;
+int check_cg_opts(grav_ctx *ctx, const grav_cg_opts *cg);
+uint64_t sections_workspace_need(const Mesh &g, int64_t n, grav_prec prec);
+int run_sections(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
+                 const double *wdepth, double lambda, const grav_cg_opts &cg,
+                 const grav_section_opts &so, double *m_out, double *m_detr,
+                 grav_cg_info *info, grav_prec prec, hipStream_t st);
 int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
                const double *wdepth, double lambda, const double *m_ref, const grav_cg_opts &cg,
                double *m_out, double *d_pred, grav_cg_info *info, grav_prec prec, hipStream_t st);

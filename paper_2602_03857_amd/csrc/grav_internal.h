@@ -53,7 +53,10 @@ struct Counter {
 // ---- launch plans -------------------------------------------------------
 
 constexpr int kBlock = 128;          // threads per block of the sweeps (2 waves)
-constexpr int kAdjLayers = 16;       // max layers per lane in the mixed adjoint sweep
+#ifndef GRAV_ADJ_LAYERS
+#define GRAV_ADJ_LAYERS 16
+#endif
+constexpr int kAdjLayers = GRAV_ADJ_LAYERS;   // max layers per lane in the mixed adjoint sweep
 
 // Layer table of the mixed sweeps (floats): [0, nz) the layer thicknesses
 // h_k = Z_{k+1} - Z_k; [nz] (as an int) the first "deep" layer; [nz+1, 2nz+1)

@@ -3,22 +3,27 @@
 // the matrix cores.
 //
 // Per workgroup: 64 observations x all 64 (padded) models, looping over
-// 4 x 4 blocks of prism columns and, inside each, over the layers.  One layer
-// step of one block:
-//   1. VALU: edge-segment terms S for the 5 x 5 vertical edges around the 16
-//      prisms, for the 64 observations (z-carry of R along each edge) -> LDS.
-//      25 edge terms serve 16 prisms (1.56 per prism).
+// blocks of kPBX x kPBY prism columns and, inside each, over the layers.  One
+// layer step of one block:
+//   1. VALU: edge-segment terms S for the (kPBX+1) x (kPBY+1) vertical edges
+//      around the block's prisms, for the 64 observations (z-carry of R along
+//      each edge) -> LDS.  A 4 x 4 block's 25 edge terms serve 16 prisms
+//      (1.56 per prism).  Larger blocks need fewer (8 x 4: 1.41), but their
+//      register and LDS footprint cost occupancy, and at 500,000 prisms x
+//      64 models they were measured no faster.
 //   2. VALU: per prism G = S00 - S10 - S01 + S11 (the (x, y) vertex parity of
 //      Eq. 1), split into bf16 hi = bf16(G), lo = bf16(G - hi) -> LDS in the
-//      MFMA A-operand order (obs x 16 prisms).
+//      MFMA A-operand order (obs x prisms).
 //   3. MFMA: four waves each own a 32 obs x 32 model block;
 //      acc += A_hi B_hi + A_hi B_lo + A_lo B_hi with v_mfma_f32_32x32x16_bf16
-//      (FP32 accumulation), B = the models pre-split into bf16 hi/lo and
-//      packed so that each lane loads its 8 operands with one 16-byte load.
+//      (FP32 accumulation), 16 prisms per instruction, B = the models
+//      pre-split into bf16 hi/lo and packed so that each lane loads its 8
+//      operands with one 16-byte load; the next step's B operands are loaded
+//      while this step's edge terms are computed.
 // After each prism-column block the FP32 MFMA accumulators are added into
-// per-thread FP64 accumulators kept in LDS, so FP32 accumulates at most 16 nz
-// terms.  The GRAV_FP32_VALU
-// variant keeps steps 1-2 (G in FP32) and contracts on the vector ALUs.
+// per-thread FP64 accumulators kept in LDS, so FP32 accumulates the terms of
+// one block only.  The GRAV_FP32_VALU variant keeps steps 1-2 (G in FP32) and
+// contracts on the vector ALUs.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -31,32 +36,43 @@ namespace grav {
 namespace {
 
 constexpr int kTileObs = 64;
-constexpr int kPB = 4;                                   // prism columns per block side
-constexpr int kEdgeSide = kPB + 1;
-constexpr int kEdgeCols = kEdgeSide * kEdgeSide;         // 25 edge columns per block
-constexpr int kColsPerWave = (kEdgeCols + 3) / 4;        // 7 (wave w takes w, w+4, ...)
-constexpr int kPrismsPerStep = kPB * kPB;                // 16 = MFMA K
+#ifndef GRAV_MULTI_PBX
+#define GRAV_MULTI_PBX 4
+#endif
+#ifndef GRAV_MULTI_PBY
+#define GRAV_MULTI_PBY 4
+#endif
+constexpr int kPBX = GRAV_MULTI_PBX;                     // prism columns per block along x
+constexpr int kPBY = GRAV_MULTI_PBY;                     // ... along y
+constexpr int kEdgeX = kPBX + 1, kEdgeY = kPBY + 1;
+constexpr int kEdgeCols = kEdgeX * kEdgeY;               // edge columns per block
+constexpr int kColsPerWave = (kEdgeCols + 3) / 4;        // wave w takes w, w+4, ...
+constexpr int kPrismsPerStep = kPBX * kPBY;              // prisms per layer step
+constexpr int kKSteps = kPrismsPerStep / 16;             // MFMA K = 16 per instruction
 constexpr int kModels = 64;
+static_assert(kPrismsPerStep % 16 == 0, "prisms per step must fill whole MFMA K blocks");
+static_assert(kPBX % 4 == 0, "each of the four waves forms kPBX / 4 prism rows");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Packed bf16 hi/lo models: index ((blk * nz + k) * 64 + j) * 16 + p, with
-// blk = bi * nby + bj the 4x4 prism-column block and p = ii * 4 + jj inside it.
+// Packed bf16 hi/lo models: index ((blk * nz + k) * 64 + j) * P + p, with
+// P = kPrismsPerStep, blk = bi * nby + bj the prism-column block and
+// p = ii * kPBY + jj inside it.
 __global__ void k_pack_models_bf16(const float *__restrict__ models, int K, int nx, int ny, int nz,
                                    int nby, int64_t total, __bf16 *__restrict__ hi,
                                    __bf16 *__restrict__ lo) {
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int p = (int)(idx & 15);
-        const int j = (int)((idx >> 4) & 63);
-        const int64_t rest = idx >> 10;
+        const int p = (int)(idx % kPrismsPerStep);
+        const int j = (int)((idx / kPrismsPerStep) & 63);
+        const int64_t rest = idx / (kPrismsPerStep * kModels);
         const int k = (int)(rest % nz);
         const int64_t blk = rest / nz;
-        const int i = (int)(blk / nby) * kPB + p / kPB;
-        const int jj = (int)(blk % nby) * kPB + p % kPB;
+        const int i = (int)(blk / nby) * kPBX + p / kPBY;
+        const int jj = (int)(blk % nby) * kPBY + p % kPBY;
         float v = 0.0f;
         if (j < K && i < nx && jj < ny) v = models[(((int64_t)i * ny + jj) * nz + k) * K + j];
         const __bf16 h = static_cast<__bf16>(v);
@@ -65,18 +81,18 @@ __global__ void k_pack_models_bf16(const float *__restrict__ models, int K, int 
     }
 }
 
-// Packed FP32 models for the VALU path: ((blk * nz + k) * 16 + p) * 64 + j.
+// Packed FP32 models for the VALU path: ((blk * nz + k) * P + p) * 64 + j.
 __global__ void k_pack_models_f32(const float *__restrict__ models, int K, int nx, int ny, int nz,
                                   int nby, int64_t total, float *__restrict__ out) {
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int j = (int)(idx & 63);
-        const int p = (int)((idx >> 6) & 15);
-        const int64_t rest = idx >> 10;
+        const int p = (int)((idx >> 6) % kPrismsPerStep);
+        const int64_t rest = idx / (kPrismsPerStep * kModels);
         const int k = (int)(rest % nz);
         const int64_t blk = rest / nz;
-        const int i = (int)(blk / nby) * kPB + p / kPB;
-        const int jj = (int)(blk % nby) * kPB + p % kPB;
+        const int i = (int)(blk / nby) * kPBX + p / kPBY;
+        const int jj = (int)(blk % nby) * kPBY + p % kPBY;
         float v = 0.0f;
         if (j < K && i < nx && jj < ny) v = models[(((int64_t)i * ny + jj) * nz + k) * K + j];
         out[idx] = v;
@@ -123,14 +139,14 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     }
 
     for (int64_t blk = b0; blk < b1; ++blk) {
-        const int i0 = (int)(blk / nby) * kPB;
-        const int j0 = (int)(blk % nby) * kPB;
+        const int i0 = (int)(blk / nby) * kPBX;
+        const int j0 = (int)(blk % nby) * kPBY;
         float cx[kColsPerWave], cy[kColsPerWave], cR[kColsPerWave];
         bool valid[kColsPerWave];
 #pragma unroll
         for (int u = 0; u < kColsPerWave; ++u) {
             const int c = wv + 4 * u;
-            const int a = i0 + c / kEdgeSide, b = j0 + c % kEdgeSide;
+            const int a = i0 + c / kEdgeY, b = j0 + c % kEdgeY;
             valid[u] = c < kEdgeCols && a <= nx && b <= ny;
             const int ac = a <= nx ? a : nx, bc = b <= ny ? b : ny;
             cx[u] = column_offset(xn[ac], xo);
@@ -140,6 +156,18 @@ __global__ __launch_bounds__(256) void k_forward_multi(
         }
         float zt = ztop, zzt = ztop * ztop;
         for (int k = 0; k < nz; ++k) {
+            // this step's model operands, loaded while the edge terms compute
+            bf16x8 bh[kKSteps], bl[kKSteps];
+            if (kMfma) {
+                const int l = lo_;
+                const int64_t bo =
+                    ((blk * nz + k) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
+#pragma unroll
+                for (int kk = 0; kk < kKSteps; ++kk) {
+                    bh[kk] = *reinterpret_cast<const bf16x8 *>(bhi + bo + 16 * kk);
+                    bl[kk] = *reinterpret_cast<const bf16x8 *>(blo + bo + 16 * kk);
+                }
+            }
             const float zb = static_cast<float>(zn[k + 1] - zo);
             const float h = hk[k];
             // phase 1: edge terms of this layer (deep layers, as in the
@@ -151,7 +179,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                     const int c = wv + 4 * u;
                     if (c < kEdgeCols) {
                         // recompute the column terms each layer rather than keeping
-                        // those of all seven columns live across the layer loop
+                        // those of all the wave's columns live across the layer loop
                         float xu = cx[u], yu = cy[u];
                         asm volatile("" : "+v"(xu), "+v"(yu));
                         const Column col = column_from_xy(xu, yu);
@@ -174,38 +202,46 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             zt = zb;
             zzt = zb * zb;
             __syncthreads();
-            // phase 2: prism terms of prisms (ii = wv, jj = 0..3) for observation lo_
+            // phase 2: prism terms of prism rows ii = wv, wv + 4, ... (all jj)
+            // for observation lo_
 #pragma unroll
-            for (int q = 0; q < kPB; ++q) {
-                const int e = wv * kEdgeSide + q;
-                float G = (sS[e][lo_] - sS[e + kEdgeSide][lo_]) - (sS[e + 1][lo_] - sS[e + kEdgeSide + 1][lo_]);
-                G = (i0 + wv < nx && j0 + q < ny) ? G : 0.0f;
-                const int p = wv * kPB + q;
-                if (kMfma) {
-                    const __bf16 h16 = static_cast<__bf16>(G);
-                    sAhi[lo_][p] = h16;
-                    sAlo[lo_][p] = static_cast<__bf16>(G - static_cast<float>(h16));
-                } else {
-                    sA32[lo_][p] = G;
+            for (int r = 0; r < kPBX / 4; ++r) {
+                const int ii = wv + 4 * r;
+#pragma unroll
+                for (int q = 0; q < kPBY; ++q) {
+                    const int e = ii * kEdgeY + q;
+                    float G = (sS[e][lo_] - sS[e + kEdgeY][lo_]) -
+                              (sS[e + 1][lo_] - sS[e + kEdgeY + 1][lo_]);
+                    G = (i0 + ii < nx && j0 + q < ny) ? G : 0.0f;
+                    const int p = ii * kPBY + q;
+                    if (kMfma) {
+                        const __bf16 h16 = static_cast<__bf16>(G);
+                        sAhi[lo_][p] = h16;
+                        sAlo[lo_][p] = static_cast<__bf16>(G - static_cast<float>(h16));
+                    } else {
+                        sA32[lo_][p] = G;
+                    }
                 }
             }
             if (!kMfma) {
                 const float4 *src = reinterpret_cast<const float4 *>(
                     b32 + ((blk * nz + k) * kPrismsPerStep) * kModels);
-                reinterpret_cast<float4 *>(&sB32[0][0])[t] = src[t];
+                for (int q = t; q < kPrismsPerStep * kModels / 4; q += 256)
+                    reinterpret_cast<float4 *>(&sB32[0][0])[q] = src[q];
             }
             __syncthreads();
-            // phase 3: contraction over the 16 prisms of this step
+            // phase 3: contraction over the prisms of this step
             if (kMfma) {
                 const int l = lo_;
-                const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(&sAhi[r0 + (l & 31)][(l >> 5) * 8]);
-                const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(&sAlo[r0 + (l & 31)][(l >> 5) * 8]);
-                const int64_t bo = ((blk * nz + k) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(bhi + bo);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(blo + bo);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bh, acc, 0, 0, 0);
+#pragma unroll
+                for (int kk = 0; kk < kKSteps; ++kk) {
+                    const int kc = 16 * kk + (l >> 5) * 8;
+                    const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(&sAhi[r0 + (l & 31)][kc]);
+                    const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(&sAlo[r0 + (l & 31)][kc]);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bh[kk], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bl[kk], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bh[kk], acc, 0, 0, 0);
+                }
             } else {
 #pragma unroll
                 for (int p = 0; p < kPrismsPerStep; ++p) {
@@ -278,8 +314,8 @@ struct MultiPlan {
 
 MultiPlan plan_multi(const Mesh &g, int64_t n) {
     MultiPlan p;
-    p.nbx = (int)cdiv(g.nx, kPB);
-    p.nby = (int)cdiv(g.ny, kPB);
+    p.nbx = (int)cdiv(g.nx, kPBX);
+    p.nby = (int)cdiv(g.ny, kPBY);
     p.nblk = (int64_t)p.nbx * p.nby;
     p.ntile = cdiv(n, kTileObs);
     int64_t nchunk = cdiv(4096, p.ntile);

@@ -137,12 +137,22 @@ __device__ __forceinline__ void adjoint_obs_range(
     int k0, int cnt, const double *__restrict__ ox, const double *__restrict__ oy,
     const double *__restrict__ oz, const double *__restrict__ v, int64_t o0, int64_t o1,
     double (&acc)[kAdjLayers]) {
+    // the next observation's coordinates and weight are loaded while this
+    // one's layers compute (index clamped at the part's last observation)
+    if (o0 >= o1) return;
+    double xq = ox[o0], yq = oy[o0], zq = oz[o0], vq = v[o0];
     for (int64_t o = o0; o < o1; ++o) {
+        const double xo = xq, yo = yq, zo = zq, vo = vq;
+        const int64_t on = o + 1 < o1 ? o + 1 : o;
+        xq = ox[on];
+        yq = oy[on];
+        zq = oz[on];
+        vq = v[on];
         int cnt_o = cnt;
         const float *zr_o = zrel, *hk_o = hk;
         asm volatile("" : "+s"(cnt_o), "+s"(zr_o), "+s"(hk_o));
-        adjoint_obs<kDeep>(X, Y, global_ptr(zr_o), global_ptr(hk_o), zn0, k0, cnt_o, ox[o], oy[o],
-                           oz[o], v[o], acc);
+        adjoint_obs<kDeep>(X, Y, global_ptr(zr_o), global_ptr(hk_o), zn0, k0, cnt_o, xo, yo, zo,
+                           vo, acc);
     }
 }
 

@@ -215,7 +215,15 @@ __global__ __launch_bounds__(kBlock) void k_forward_f64(
 // Mixed adjoint sweep.  Lane = (node column, chunk of <= kAdjLayers layers).
 // Bounded to 64 VGPRs so that 8 waves fit on a SIMD (the few values it spills
 // are read once per observation, outside the layer steps).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+#ifndef GRAV_ADJ_WAVES
+#define GRAV_ADJ_WAVES 8
+#endif
+#if GRAV_ADJ_WAVES > 0
+#define GRAV_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(GRAV_ADJ_WAVES, GRAV_ADJ_WAVES)))
+#else
+#define GRAV_ADJ_OCCUPANCY
+#endif
+__global__ __launch_bounds__(kBlock) GRAV_ADJ_OCCUPANCY
 void k_adjoint_mixed(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,

@@ -1,7 +1,7 @@
 // Regional-residual separation: least-squares polynomial trend surface of
 // degree 1 or 2 in the horizontal station coordinates (the second-degree
-// trend removal of the paper's field workflow, Section 3.2; the same fit over
-// the whole domain joins independently inverted sections, Section 4.4).
+// trend removal of the paper's field workflow, Section 2.2; the same fit over
+// the whole domain joins independently inverted sections, Section 4.5).
 //
 // The fit is done in the centred, scaled frame u = (x - x0) / L,
 // w = (y - y0) / L (bounding-box centre, half the larger side), where the

@@ -1,0 +1,137 @@
+"""GPU parity of the regional section workflow (grav_invert_sections; paper
+Section 4.5 with the trend separation of Section 2.2) against the FP64
+oracle (``oracle.sections``: dense Cholesky solves of Eq. 11 per section).
+
+The inputs are a seeded synthetic regional survey (``workloads.regional_sections``:
+three ellipsoids straddling the section boundaries, a second-degree regional
+field larger than the local anomaly, 1 % noise); the data are built with the
+oracle's forward operator.  The library solves each section by CG, so the
+comparison is CG against the exact solve: GRAV_FP64 to a relative residual of
+1e-12 (models within 1e-7 relative L2), GRAV_MIXED to 1e-8.  The mixed
+solve is the exact solve of a slightly perturbed data-space system, so its
+density error grows with the condition number kappa(A) of A = G C G^T +
+lambda I: the 1e-4 density target holds at the conditioning of the 32 x 32 x
+16 dyke inversion (kappa 2.4e3), and the cap scales linearly with the largest
+section kappa above 2.5e3 (kappa from the oracle's dense A)."""
+import numpy as np
+import pytest
+
+from oracle import inversion, prism, sections
+import workloads
+from tests._util import load_package, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    pkg = load_package()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(device=0)
+    yield c
+    c.close()
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+@pytest.fixture(scope="module")
+def regional():
+    p = workloads.regional_sections()
+    d = prism.forward(p.mesh, p.obs, p.m)
+    d_obs = inversion.add_noise(d + workloads.regional_field(p), p.noise_draws, p.noise_level)
+    return p, d_obs
+
+
+def _max_section_kappa(p):
+    ys = p.extra["ysplit"]
+    sec = sections.section_of_stations(p.mesh, p.obs, ys)
+    kappa = 0.0
+    for s in range(len(ys) - 1):
+        so = p.obs.take(np.flatnonzero(sec == s))
+        sm = sections.sub_mesh(p.mesh, ys[s], ys[s + 1])
+        cov = inversion.covariance_from_weights(p.wdepth[sections.cell_slice(p.mesh, ys[s], ys[s + 1])])
+        G = np.stack([prism.sensitivity_row(sm, so.x[o], so.y[o], so.z[o]) for o in range(so.n)])
+        A = (G * cov) @ G.T
+        A += inversion.lambda_rule(float(np.trace(A)), so.n) * np.eye(so.n)
+        kappa = max(kappa, float(np.linalg.cond(A)))
+    return kappa
+
+
+SETTINGS = [
+    dict(data_degree=2, data_scope="section", model_degree=2),
+    dict(data_degree=1, data_scope="domain", model_degree=1),
+    dict(data_degree=0, data_scope="section", model_degree=0),
+]
+
+
+@pytest.mark.parametrize("prec_name,tol,cap", [("GRAV_FP64", 1e-12, 1e-7),
+                                               ("GRAV_MIXED", 1e-8, 1e-4)])
+@pytest.mark.parametrize("setting", SETTINGS)
+def test_sections_match_oracle(g, ctx, regional, setting, prec_name, tol, cap):
+    p, d_obs = regional
+    ysplit = [int(j) for j in p.extra["ysplit"]]
+    print(f"[sections] {prec_name} {setting} ysplit={ysplit}", flush=True)
+    ref_m, ref_r, ref_info = sections.invert_sections(p.mesh, p.obs, d_obs, p.wdepth, ysplit,
+                                                      lam=-1.0, **setting)
+    mesh = g.DeviceMesh.from_mesh(p.mesh)
+    obs = g.DeviceObs.from_survey(p.obs)
+    m, mr, info = ctx.invert_sections(mesh, obs, _t(d_obs), _t(p.wdepth), ysplit, lam=-1.0,
+                                      tol=tol, max_iter=20000, prec=getattr(g, prec_name),
+                                      **setting)
+    e_m, e_r = rel_l2(to_np(m), ref_m), rel_l2(to_np(mr), ref_r)
+    if prec_name == "GRAV_MIXED":
+        cap *= max(1.0, _max_section_kappa(p) / 2.5e3)
+    print(f"[sections] combined model rel L2 {e_m:.3e}, detrended {e_r:.3e} (cap {cap:.2e}), "
+          f"iterations {[i['iters'] for i in info]}", flush=True)
+    assert e_m <= cap and e_r <= cap
+    for s, (a, b) in enumerate(zip(info, ref_info)):
+        assert a["relres"] <= tol
+        assert abs(a["lambda_used"] - b["lam"]) <= 1e-6 * b["lam"], f"section {s} lambda"
+    # each section's block of the combined model is that section's own solve
+    if setting["model_degree"] == 0:
+        assert np.array_equal(to_np(m), to_np(mr))
+
+
+def test_one_section_is_the_plain_inversion(g, ctx, regional):
+    p, d_obs = regional
+    mesh = g.DeviceMesh.from_mesh(p.mesh)
+    obs = g.DeviceObs.from_survey(p.obs)
+    m, _, info = ctx.invert_sections(mesh, obs, _t(d_obs), _t(p.wdepth), [0, p.mesh.ny],
+                                     data_degree=0, model_degree=0, lam=-1.0, tol=1e-10,
+                                     max_iter=5000, prec=g.GRAV_FP64, detrend=False)
+    m1, _, info1 = ctx.invert(mesh, obs, _t(d_obs), _t(p.wdepth), lam=-1.0, tol=1e-10,
+                              max_iter=5000, prec=g.GRAV_FP64)
+    assert np.array_equal(to_np(m), to_np(m1))
+    assert info[0]["iters"] == info1["iters"]
+
+
+def test_sections_errors(g, ctx, regional):
+    p, d_obs = regional
+    mesh = g.DeviceMesh.from_mesh(p.mesh)
+    obs = g.DeviceObs.from_survey(p.obs)
+    d, w = _t(d_obs), _t(p.wdepth)
+    ny = p.mesh.ny
+    for bad in ([0, 5, 5, ny], [1, 6, ny], [0, 6, ny - 1], [0]):
+        with pytest.raises(g.GravError) as ei:
+            ctx.invert_sections(mesh, obs, d, w, bad, prec=g.GRAV_FP64)
+        assert ei.value.code == g.GRAV_EINVAL
+    # a section that holds no station: all stations moved into y < yn[6]
+    y = np.minimum(p.obs.y, p.mesh.yn[6] - 1.0)
+    obs2 = g.DeviceObs(p.obs.x, y, p.obs.z)
+    with pytest.raises(g.GravError) as ei:
+        ctx.invert_sections(mesh, obs2, d, w, [0, 6, 12, ny], prec=g.GRAV_FP64)
+    assert ei.value.code == g.GRAV_EINVAL and "no stations" in str(ei.value)
+    # an iteration cap reached in a section is a warning with valid outputs
+    m, mr, info = ctx.invert_sections(mesh, obs, d, w, [0, 6, 12, ny], tol=1e-14, max_iter=3,
+                                      prec=g.GRAV_FP64)
+    assert all(i["iters"] == 3 for i in info)
+    assert np.all(np.isfinite(to_np(m))) and np.all(np.isfinite(to_np(mr)))

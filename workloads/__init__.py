@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "Mesh", "Survey", "Problem", "regular_mesh", "cell_centres",
     "dykes_32x32x16", "ellipsoids_100x100x50", "smoothed_box_models", "paper_scale", "serving_stream",
-    "random_case", "ellipsoid_model", "dyke_model",
+    "random_case", "ellipsoid_model", "dyke_model", "regional_sections", "regional_field",
 ]
 
 
@@ -340,6 +340,49 @@ def _stream_request_builder(kind, n_target, cells_target, seed):
                        cg_iters=200 if kind == "inversion" else 0,
                        extra=dict(kind=kind))
     return build
+
+
+def regional_sections(seed: int = 45, nx: int = 10, ny: int = 18, nz: int = 6,
+                      n_obs: int = 320, cell: float = 100.0, nsec: int = 3) -> Problem:
+    """Small regional survey for the section workflow, shaped like the paper's
+    regional example (a domain longer north-south (y) than east-west, about
+    1.7 : 1, divided into adjoining sections along y): a regular mesh of
+    ``cell``-metre cubes, ``n_obs`` stations on a jittered grid over the
+    footprint at heights U[0, 30] m, three random ellipsoids (contrast
+    U[-400, 400] kg/m^3, semi-axes 0.1-0.45 of the width, so bodies straddle
+    section boundaries), and a regional field: a second-degree polynomial in
+    the normalised station coordinates u = (x - xc) / (width / 2),
+    w = (y - yc) / (length / 2) with coefficients U[-1, 1] x 3e-5 m/s^2 (about
+    3 mGal, larger than the local anomaly).  ``extra``: ysplit (nsec equal
+    sections of whole cell rows) and regional_coef (constant, u, w, u^2, u w,
+    w^2).  1 % noise draws; w = (z + 25 m)^-1."""
+    rng = np.random.default_rng(seed)
+    mesh = regular_mesh(nx, ny, nz, cell, cell, cell)
+    wx, wy = nx * cell, ny * cell
+    gx = max(2, int(round(math.sqrt(n_obs * wx / wy))))
+    gy = max(2, -(-n_obs // gx))
+    ox = (np.arange(gx * gy) % gx + 0.5) * (wx / gx)
+    oy = (np.arange(gx * gy) // gx + 0.5) * (wy / gy)
+    keep = rng.permutation(gx * gy)[:n_obs]
+    ox = ox[keep] + rng.uniform(-0.3, 0.3, n_obs) * (wx / gx)
+    oy = oy[keep] + rng.uniform(-0.3, 0.3, n_obs) * (wy / gy)
+    oz = mesh.zn[0] - rng.uniform(0.0, 30.0, n_obs)
+    obs = Survey(ox, oy, oz)
+    m = ellipsoid_model(mesh, rng, 3, 0.1 * wx, 0.45 * wx)
+    coef = rng.uniform(-1.0, 1.0, 6) * 3e-5
+    ysplit = np.round(np.linspace(0, ny, nsec + 1)).astype(int)
+    return Problem(f"regional_sections-{seed}", mesh, obs, m, wdepth=depth_weights(mesh, 25.0),
+                   noise_draws=rng.standard_normal(n_obs), noise_level=0.01,
+                   extra=dict(ysplit=ysplit, regional_coef=coef,
+                              centre=(0.5 * wx, 0.5 * wy), half=(0.5 * wx, 0.5 * wy)))
+
+
+def regional_field(p: Problem) -> np.ndarray:
+    """The regional polynomial of ``regional_sections`` at the stations."""
+    c = p.extra["regional_coef"]
+    u = (p.obs.x - p.extra["centre"][0]) / p.extra["half"][0]
+    w = (p.obs.y - p.extra["centre"][1]) / p.extra["half"][1]
+    return c[0] + c[1] * u + c[2] * w + c[3] * u * u + c[4] * u * w + c[5] * w * w
 
 
 def random_case(seed: int, nx: int, ny: int, nz: int, n_obs: int, *,
