@@ -123,7 +123,8 @@ int grav_ctx_create(grav_ctx **ctx, const grav_ctx_opts *opts);
 void grav_ctx_destroy(grav_ctx *ctx);
 
 /* Text of the last error on this context ("" if none).  Owned by the context,
- * valid until the next call on it.  NULL ctx: the last context-creation error. */
+ * valid until the next call on it.  NULL ctx: the last error of grav_ctx_create or
+ * grav_forward_static on the calling thread. */
 const char *grav_last_error(const grav_ctx *ctx);
 
 /* Device workspace bytes that `op` needs for this shape and precision (K =
@@ -304,6 +305,31 @@ int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs
                        const float *models, int32_t K, float *D, grav_prec prec,
                        grav_stream stream);
 
+/* Size of the library's static device scratch buffer (bytes, per device). */
+#define GRAV_STATIC_SCRATCH_BYTES ((uint64_t)128 << 20)
+
+/* Forward product d = G m without a context or any device allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same operator,
+ * arguments, launch plan and kernels as grav_forward, so the result is
+ * bitwise that of grav_forward for the same inputs and precision.
+ *   Runs on the calling thread's current HIP device.  Its scratch memory is a
+ *   static device array of GRAV_STATIC_SCRATCH_BYTES that the library holds
+ *   on every device it runs on until the process ends; the call allocates and
+ *   frees nothing (no hipMalloc/hipFree, no allocating library call).
+ *   Problems whose forward workspace (grav_workspace_bytes(.., GRAV_OP_FORWARD,
+ *   ..) plus 16 KiB) exceeds it are rejected with GRAV_ENOMEM before any work
+ *   is enqueued (the paper-scale 178,797 x 3,307,500 forward needs 91 MiB).
+ *   validate != 0: the arguments are checked on the device first and the call
+ *   waits for that check on `stream` (as with a validating context); 0: the
+ *   call is fully asynchronous and the caller guarantees the preconditions.
+ *   All calls on one device share that device's buffer and leave their
+ *   intermediate values in it: calls that may overlap in time on one device
+ *   (different streams or threads) race and must be serialised by the caller.
+ * Errors: GRAV_EINVAL, GRAV_ENOMEM (problem too large for the buffer),
+ * GRAV_EDEVICE; grav_last_error(NULL) gives the reason (per thread). */
+int grav_forward_static(const grav_mesh *mesh, const grav_obs *obs, const double *m, double *d,
+                        grav_prec prec, int32_t validate, grav_stream stream);
 
 
 /* ---------------------------------------------------------------------------

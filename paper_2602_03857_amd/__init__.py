@@ -14,13 +14,14 @@ import os
 from ._lib import (  # noqa: F401
     LIB_PATH, lib, GravError, GRAV_OK, GRAV_EINVAL, GRAV_ENOMEM, GRAV_EDEVICE, GRAV_ENOCONV,
     GRAV_EBUSY, GRAV_ECANCELED, GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU, GRAV_GAMMA,
+    GRAV_STATIC_SCRATCH_BYTES,
     OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND,
     OP_SECTIONS, GRAV_TREND_SECTION, GRAV_TREND_DOMAIN,
     CMesh, CObs, CtxOpts, CgOpts, CgInfo,
 )
-from .api import Context, DeviceMesh, DeviceObs, workspace_bytes  # noqa: F401
+from .api import Context, DeviceMesh, DeviceObs, forward_static, workspace_bytes  # noqa: F401
 from .serve import Server  # noqa: F401
 
-__all__ = ["Context", "Server", "DeviceMesh", "DeviceObs", "workspace_bytes",
+__all__ = ["Context", "Server", "DeviceMesh", "DeviceObs", "forward_static", "workspace_bytes",
            "GravError", "lib",
            "GRAV_FP64", "GRAV_MIXED", "GRAV_MIXED_BF16X3", "GRAV_FP32_VALU", "GRAV_GAMMA"]

@@ -11,6 +11,7 @@ GRAV_FP64, GRAV_MIXED, GRAV_MIXED_BF16X3, GRAV_FP32_VALU = range(4)
 OP_FORWARD, OP_ADJOINT, OP_DATASPACE, OP_TRACE, OP_INVERT, OP_FORWARD_MULTI, OP_TREND, OP_SECTIONS = range(8)
 GRAV_TREND_SECTION, GRAV_TREND_DOMAIN = range(2)
 GRAV_GAMMA = 6.674e-11
+GRAV_STATIC_SCRATCH_BYTES = 128 << 20
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -108,6 +109,7 @@ def _load():
         "grav_invert_sections": (ctypes.c_int, [vp, P(CMesh), P(CObs), vp, vp, dbl, P(CgOpts),
                                                 P(SectionOpts), vp, vp, P(CgInfo), ctypes.c_int,
                                                 vp]),
+        "grav_forward_static": (ctypes.c_int, [P(CMesh), P(CObs), vp, vp, ctypes.c_int, i32, vp]),
         "grav_server_create": (ctypes.c_int, [P(vp), P(ServerOpts)]),
         "grav_server_submit": (ctypes.c_int, [vp, P(GravRequest), P(ctypes.c_uint64)]),
         "grav_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, P(i32), P(RequestInfo)]),
@@ -132,7 +134,7 @@ EXPORTED = [
     "grav_ctx_opts_default", "grav_ctx_create", "grav_ctx_destroy", "grav_last_error",
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
     "grav_trend_surface",
-    "grav_invert", "grav_invert_sections", "grav_forward_multi", "grav_set_timing", "grav_kernel_time",
+    "grav_invert", "grav_invert_sections", "grav_forward_multi", "grav_forward_static", "grav_set_timing", "grav_kernel_time",
     "grav_reset_timing", "grav_issue_rates", "grav_server_create", "grav_server_submit", "grav_server_poll",
     "grav_server_wait", "grav_server_cancel", "grav_server_destroy",
 ]

@@ -81,6 +81,24 @@ def workspace_bytes(nx, ny, nz, n, op=OP_FORWARD, prec=GRAV_MIXED, K=0) -> int:
     return int(lib.grav_workspace_bytes(nx, ny, nz, n, op, prec, K))
 
 
+def forward_static(mesh: DeviceMesh, obs: DeviceObs, m, d=None, prec=GRAV_MIXED, validate=True,
+                   stream=None):
+    """d = G m through grav_forward_static (no context; the library's static
+    device scratch buffer), on mesh.device.  m: (M,) float64 device tensor."""
+    dev = mesh.device
+    _check(m, torch.float64, mesh.ncells, "m", dev)
+    if d is None:
+        d = torch.empty(obs.n, dtype=torch.float64, device=dev)
+    _check(d, torch.float64, obs.n, "d", dev)
+    with torch.cuda.device(dev):
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc = lib.grav_forward_static(ctypes.byref(mesh.c), ctypes.byref(obs.c), m.data_ptr(),
+                                     d.data_ptr(), prec, 1 if validate else 0,
+                                     ctypes.c_void_p(st.cuda_stream))
+    if rc != GRAV_OK:
+        raise GravError(rc, lib.grav_last_error(None).decode())
+    return d
+
 
 class Context:
     """A library context: one device, one workspace, one call at a time."""

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libgrav.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["api.hip", "sweeps.hip", "vec.hip", "solver.hip", "multi.hip", "server.hip", "trend.hip", "probe.hip",
-           "sections.hip"]
+           "noalloc.hip", "sections.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.

@@ -21,6 +21,8 @@ extern "C" int grav_reset_timing(grav_ctx *ctx);
 
 namespace grav {
 
+void set_context_free_error(const std::string &msg) { g_create_error = msg; }
+
 int fail(grav_ctx *ctx, int code, const std::string &msg) {
     if (ctx) ctx->err = msg;
     return code;

@@ -45,6 +45,8 @@ struct ArrayCheck {
 };
 
 int fail(grav_ctx *ctx, int code, const std::string &msg);
+// Error text of the calls that take no context (grav_last_error(NULL)), per thread.
+void set_context_free_error(const std::string &msg);
 int hip_fail(grav_ctx *ctx, hipError_t e, const char *where);
 Arena ctx_arena(grav_ctx *ctx);
 int check_geometry_host(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs);
