@@ -21,8 +21,9 @@
 //      operands with one 16-byte load; the next step's B operands are loaded
 //      while this step's edge terms are computed.
 // After each prism-column block the FP32 MFMA accumulators are added into
-// per-thread FP64 accumulators kept in LDS, so FP32 accumulates the terms of
-// one block only.  The GRAV_FP32_VALU variant keeps steps 1-2 (G in FP32) and
+// per-thread FP64 accumulators (four in registers, twelve in LDS: 128 VGPRs
+// and 35 KB of LDS allow four waves per SIMD), so FP32 accumulates the terms
+// of one block only.  The GRAV_FP32_VALU variant keeps steps 1-2 (G in FP32) and
 // contracts on the vector ALUs.
 #include <hip/hip_runtime.h>
 
@@ -99,6 +100,18 @@ __global__ void k_pack_models_f32(const float *__restrict__ models, int K, int n
     }
 }
 
+#ifndef GRAV_MULTI_REG_ACC
+#define GRAV_MULTI_REG_ACC 4
+#endif
+constexpr int kRegAcc = GRAV_MULTI_REG_ACC;   // FP64 accumulators per thread held in registers
+static_assert(kRegAcc >= 0 && kRegAcc < 16, "at least one accumulator lives in LDS");
+
+// Accumulator v of thread t (v is a compile-time index after unrolling).
+__device__ __forceinline__ double &acc_ref(double (&r)[kRegAcc > 0 ? kRegAcc : 1],
+                                           double (&lds)[16 - kRegAcc][256], int v, int t) {
+    return v < kRegAcc ? r[v] : lds[v - kRegAcc][t];
+}
+
 template <bool kMfma>
 __global__ __launch_bounds__(256) void k_forward_multi(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
@@ -112,7 +125,11 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     __shared__ __attribute__((aligned(16))) __bf16 sAlo[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sA32[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sB32[kPrismsPerStep][kModels];
-    __shared__ double sAcc[16][256];    // per-thread FP64 accumulators (column t)
+    // per-thread FP64 accumulators: the first kRegAcc in registers, the rest
+    // in LDS (column t), which keeps the block's LDS small enough for four
+    // blocks per CU
+    __shared__ double sAcc[16 - kRegAcc][256];
+    double rAcc[kRegAcc > 0 ? kRegAcc : 1];
 
     const int chunk = (int)(blockIdx.x % nchunk);
     const int64_t tile = blockIdx.x / nchunk;
@@ -135,7 +152,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     for (int v = 0; v < 16; ++v) {
         acc[v] = 0.0f;
         acc32[v] = 0.0f;
-        sAcc[v][t] = 0.0;
+        acc_ref(rAcc, sAcc, v, t) = 0.0;
     }
 
     for (int64_t blk = b0; blk < b1; ++blk) {
@@ -254,10 +271,10 @@ __global__ __launch_bounds__(256) void k_forward_multi(
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             if (kMfma) {
-                sAcc[v][t] += static_cast<double>(acc[v]);
+                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc[v]);
                 acc[v] = 0.0f;
             } else {
-                sAcc[v][t] += static_cast<double>(acc32[v]);
+                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc32[v]);
                 acc32[v] = 0.0f;
             }
         }
@@ -269,11 +286,13 @@ __global__ __launch_bounds__(256) void k_forward_multi(
         for (int v = 0; v < 16; ++v) {
             const int row = r0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
             const int64_t og = tile * kTileObs + row;
-            if (og < n) partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] = sAcc[v][t];
+            if (og < n)
+                partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] = acc_ref(rAcc, sAcc, v, t);
         }
     } else if (o < n) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = sAcc[v][t];
+        for (int v = 0; v < 16; ++v)
+            partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = acc_ref(rAcc, sAcc, v, t);
     }
 }
 
