@@ -438,7 +438,9 @@ def run_cg_compare(args) -> int:
 def run_profile_op(args) -> int:
     """Only one operator at paper scale (178,797 obs x 3,307,500 prisms,
     GRAV_MIXED), args.steps times after args.warmup untimed calls: the target
-    of the counter and kernel-trace runs of a single sweep."""
+    of the counter and kernel-trace runs of a single sweep ("multi": the
+    split-bf16 multi-model forward of 64 models at 10,000 obs x 500,000
+    prisms instead)."""
     import torch
     import paper_2602_03857_amd as g
     p = workloads.paper_scale()
@@ -456,6 +458,16 @@ def run_profile_op(args) -> int:
         "dataspace": ("adjoint_mixed", lambda c: c.dataspace_apply(mesh, obs, w, 1e-12, v, out_n,
                                                                    prec=g.GRAV_MIXED)),
     }
+    if args.profile_op == "multi":
+        # 64 density models on the 100 x 100 x 50 mesh with 10,000 stations
+        p3 = workloads.ellipsoids_100x100x50()
+        mesh = g.DeviceMesh.from_mesh(p3.mesh, dev)
+        obs = g.DeviceObs.from_survey(p3.obs, dev)
+        models = torch.as_tensor(workloads.smoothed_box_models(p3.mesh).astype(np.float32),
+                                 device=dev)
+        D = torch.empty((p3.obs.n, models.shape[1]), dtype=torch.float32, device=dev)
+        ops["multi"] = ("multi_bf16x3", lambda c: c.forward_multi(mesh, obs, models, D,
+                                                                  prec=g.GRAV_MIXED_BF16X3))
     kname, call = ops[args.profile_op]
     with g.Context(0, validate=False) as ctx:
         ctx.set_timing(True)
@@ -513,7 +525,7 @@ def main() -> int:
                     help="measure the instruction issue rates behind the roofline weights")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--profile-op", choices=("forward", "adjoint", "dataspace"),
+    ap.add_argument("--profile-op", choices=("forward", "adjoint", "dataspace", "multi"),
                     help="only time this operator at paper scale (profiling runs)")
     ap.add_argument("--serve-extras-requests", type=int, default=60,
                     help="requests of the serving stream replayed in the default run (0 = none)")

@@ -73,7 +73,13 @@ typedef enum {
 typedef enum {
     GRAV_FP64 = 0,          /* plain path: every corner term Psi(node - obs) in FP64 */
     GRAV_MIXED = 1,         /* FP32 edge-segment terms from FP64 coordinate differences,
-                               FP64 alternating sums, accumulation and CG dot products */
+                               FP64 alternating sums, accumulation and CG dot products.
+                               Accurate to 1e-5 relative for stations over and around
+                               the mesh (tested to half its width beyond it).  Far
+                               outside it (distance R >> mesh width L) the edge terms
+                               cancel by about (R/L)^2, and a result is only good to
+                               16 eps32 x the sum of the magnitudes of its terms:
+                               use GRAV_FP64 for such stations. */
     GRAV_MIXED_BF16X3 = 2,  /* multi-model only: FP32 G tiles split into bf16 hi+lo,
                                3-product split-BF16 MFMA, FP32 accumulation */
     GRAV_FP32_VALU = 3      /* multi-model only: the same FP32 G tiles contracted on the
