@@ -53,8 +53,10 @@ constexpr int kKSteps = kPrismsPerStep / 16;             // MFMA K = 16 per inst
 constexpr int kModels = 64;
 static_assert(kPrismsPerStep % 16 == 0, "prisms per step must fill whole MFMA K blocks");
 static_assert(kPBX % 4 == 0, "each of the four waves forms kPBX / 4 prism rows");
+static_assert(kPBY == 4, "a prism row is stored as one 8-byte (bf16) or 16-byte (FP32) write");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -221,23 +223,30 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             __syncthreads();
             // phase 2: prism terms of prism rows ii = wv, wv + 4, ... (all jj)
             // for observation lo_
+            // A row's kPBY prisms are stored with one vector write per array
+            // (scattered 2-byte writes to rows 32 bytes apart conflict on the
+            // LDS banks).
 #pragma unroll
             for (int r = 0; r < kPBX / 4; ++r) {
                 const int ii = wv + 4 * r;
+                __bf16 hi4[kPBY], lo4[kPBY];
+                float g4[kPBY];
 #pragma unroll
                 for (int q = 0; q < kPBY; ++q) {
                     const int e = ii * kEdgeY + q;
                     float G = (sS[e][lo_] - sS[e + kEdgeY][lo_]) -
                               (sS[e + 1][lo_] - sS[e + kEdgeY + 1][lo_]);
                     G = (i0 + ii < nx && j0 + q < ny) ? G : 0.0f;
-                    const int p = ii * kPBY + q;
-                    if (kMfma) {
-                        const __bf16 h16 = static_cast<__bf16>(G);
-                        sAhi[lo_][p] = h16;
-                        sAlo[lo_][p] = static_cast<__bf16>(G - static_cast<float>(h16));
-                    } else {
-                        sA32[lo_][p] = G;
-                    }
+                    g4[q] = G;
+                    hi4[q] = static_cast<__bf16>(G);
+                    lo4[q] = static_cast<__bf16>(G - static_cast<float>(hi4[q]));
+                }
+                const int p0 = ii * kPBY;
+                if (kMfma) {
+                    *reinterpret_cast<bf16x4 *>(&sAhi[lo_][p0]) = *reinterpret_cast<bf16x4 *>(hi4);
+                    *reinterpret_cast<bf16x4 *>(&sAlo[lo_][p0]) = *reinterpret_cast<bf16x4 *>(lo4);
+                } else {
+                    *reinterpret_cast<float4 *>(&sA32[lo_][p0]) = *reinterpret_cast<float4 *>(g4);
                 }
             }
             if (!kMfma) {
