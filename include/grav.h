@@ -351,7 +351,11 @@ int grav_forward_static(const grav_mesh *mesh, const grav_obs *obs, const double
  * requests, so each active inversion advances one CG iteration per step and
  * requests that arrive meanwhile join at the next step.  A request's launch
  * plan depends only on its own shape, so its result is bitwise the same alone
- * and in any mix, and the same as grav_forward / grav_invert (GRAV_MIXED).
+ * and in any mix.  A forward request is bitwise the same as grav_forward
+ * (GRAV_MIXED).  An inversion's adjoint splits the observations into fewer
+ * parts than grav_invert's does once a problem has more than a few thousand
+ * observations (a batched launch fills the GPU with every request's waves),
+ * so it agrees with grav_invert to rounding there and bitwise below that.
  * Requests may be submitted from any thread.
  * ------------------------------------------------------------------------ */
 typedef struct grav_server grav_server;

@@ -89,7 +89,9 @@ struct NodeAdjointPlan {
 };
 
 ForwardPlan plan_forward(int64_t ncols, int64_t n);
-AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n);
+// target_waves, max_partial_bytes: 0 = the single-call defaults
+AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n, int64_t target_waves = 0,
+                         int64_t max_partial_bytes = 0);
 NodeAdjointPlan plan_adjoint_nodes(int64_t nnodes, int64_t n);
 ForwardPlan plan_trace(int nx, int64_t n);
 

@@ -346,7 +346,10 @@ MultiPlan plan_multi(const Mesh &g, int64_t n) {
     p.nby = (int)cdiv(g.ny, kPBY);
     p.nblk = (int64_t)p.nbx * p.nby;
     p.ntile = cdiv(n, kTileObs);
-    int64_t nchunk = cdiv(4096, p.ntile);
+    // a multiple of 8 chunks: block b works on chunk b mod nchunk and runs on
+    // XCD b mod 8, so each XCD only ever reads its own chunks' packed models
+    // and the tiles working on one chunk share them in that XCD's L2
+    int64_t nchunk = cdiv(cdiv(4096, p.ntile), 8) * 8;
     if (nchunk > p.nblk) nchunk = p.nblk;
     if (nchunk < 1) nchunk = 1;
     p.blocks_per_chunk = cdiv(p.nblk, nchunk);

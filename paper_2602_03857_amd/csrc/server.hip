@@ -54,6 +54,11 @@ constexpr int kMaxActiveCap = 256;
 constexpr int kSlotScalars = 16;     // per active request in the device scalar table
 constexpr int kLambdaSlot = 6;       // lambda used by the request
 constexpr int kTraceSlot = 7;        // trace(G C G^T) when computed
+// Adjoint plan of a served request: the batched launch mixes the waves of
+// every active request, so each request needs fewer observation parts than a
+// single call to fill the GPU, and its partial sums stay small in the pool.
+constexpr int64_t kServerTargetWavesAdj = 32768;
+constexpr int64_t kServerMaxPartialBytes = int64_t(512) << 20;
 // Largest grid of one batched launch (a larger batch is split over launches).
 constexpr int64_t kMaxGridBlocks = int64_t(1) << 30;
 
@@ -180,7 +185,7 @@ size_t request_layout(Request &q, char *base) {
     q.w2 = ar.take<double>(g.nsegs());
     q.fpart = ar.take<double>((size_t)q.fp.nchunk * n);
     if (q.r.kind == GRAV_REQ_INVERT) {
-        q.ap = plan_adjoint(g.ncols(), g.nz, n);
+        q.ap = plan_adjoint(g.ncols(), g.nz, n, kServerTargetWavesAdj, kServerMaxPartialBytes);
         q.tp = plan_trace(g.nx, n);
         q.upart = ar.take<double>((size_t)q.ap.nparts * g.nsegs());
         q.U = ar.take<double>(g.nsegs());

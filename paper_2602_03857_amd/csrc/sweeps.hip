@@ -409,23 +409,29 @@ inline unsigned grid_for(int64_t len, int block = 256, int64_t cap = 8192) {
 
 // ------------------------------------------------------------------ plans
 
-// Enough equal-work waves that the last partial round of 8 waves per SIMD on
-// the 1024 SIMDs costs little (measured at the paper-scale workload: 16k ->
-// 128k waves shortens the forward sweep by 2 %, the adjoint by 3 %), chunk and
-// part counts a multiple of 8 (one residue class per XCD), capped so that
-// every chunk keeps >= 8 node columns and every observation part >= 64
-// observations and 512 MiB of partial sums.
+// Enough equal-work waves that the drain at the end of a launch (8 waves
+// per SIMD on 1024 SIMDs finish at different times) costs little: measured at
+// the paper-scale workload, 16k -> 128k waves shortens the forward sweep by
+// 2 %, and the adjoint (whose waves are longer) gains 3 % from 16k -> 57k and
+// 4.6 % more from 57k -> 143k (0.7 % more at 286k, for twice the partial
+// sums).  Chunk and part counts are a multiple of 8 (one residue class per
+// XCD), capped so that every chunk keeps >= 8 node columns and every
+// observation part >= 64 observations and 2 GiB of partial sums (1.07 GB at
+// paper scale).
 #ifndef GRAV_TARGET_WAVES_FWD
 #define GRAV_TARGET_WAVES_FWD 131072
 #endif
 #ifndef GRAV_TARGET_WAVES_ADJ
-#define GRAV_TARGET_WAVES_ADJ 32768
+#define GRAV_TARGET_WAVES_ADJ 131072
 #endif
 static constexpr int64_t kTargetWavesFwd = GRAV_TARGET_WAVES_FWD;
 static constexpr int64_t kTargetWavesAdj = GRAV_TARGET_WAVES_ADJ;
 static constexpr int64_t kMinColsPerChunk = 8;
 static constexpr int64_t kMinObsPerPart = 64;
-static constexpr int64_t kMaxPartialBytes = int64_t(512) << 20;
+#ifndef GRAV_MAX_PARTIAL_MIB
+#define GRAV_MAX_PARTIAL_MIB 2048
+#endif
+static constexpr int64_t kMaxPartialBytes = int64_t(GRAV_MAX_PARTIAL_MIB) << 20;
 
 static int64_t round8_capped(int64_t want, int64_t cap) {
     if (cap < 1) cap = 1;
@@ -456,15 +462,18 @@ ForwardPlan plan_trace(int nx, int64_t n) {
     return p;
 }
 
-AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n) {
+AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n, int64_t target_waves,
+                         int64_t max_partial_bytes) {
+    if (target_waves <= 0) target_waves = kTargetWavesAdj;
+    if (max_partial_bytes <= 0) max_partial_bytes = kMaxPartialBytes;
     AdjointPlan p;
     p.nblk_col = ceil_div(ncols, kBlock);
     p.nkc = (int)ceil_div(nz, kAdjLayers);
     const int64_t waves = p.nblk_col * p.nkc * (kBlock / 64);
     int64_t cap = n / kMinObsPerPart;
-    const int64_t mem_cap = kMaxPartialBytes / (ncols * nz * 8);
+    const int64_t mem_cap = max_partial_bytes / (ncols * nz * 8);
     if (mem_cap < cap) cap = mem_cap;
-    const int64_t parts = round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
+    const int64_t parts = round8_capped(ceil_div(target_waves, waves), cap);
     p.obs_per_part = ceil_div(n, parts);
     p.nparts = (int)ceil_div(n, p.obs_per_part);
     return p;
