@@ -292,7 +292,8 @@ typedef struct {
  *   info : HOST array of nsec entries or NULL: each section's CG summary.
  *   The call waits for completion.
  * Returns GRAV_OK, GRAV_ENOCONV (a section reached its iteration cap; all
- * outputs valid), or an error: GRAV_EINVAL also for a section without
+ * outputs valid), or an error (after which m_out and m_detrended may hold the
+ * sections finished before it): GRAV_EINVAL also for a section without
  * stations, fewer stations (or horizontal cells) than a trend surface needs,
  * or points that do not determine it; GRAV_ENOMEM below
  * grav_workspace_bytes(.., GRAV_OP_SECTIONS, ..), which bounds any split. */
