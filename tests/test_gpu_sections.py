@@ -135,3 +135,51 @@ def test_sections_errors(g, ctx, regional):
                                       prec=g.GRAV_FP64)
     assert all(i["iters"] == 3 for i in info)
     assert np.all(np.isfinite(to_np(m))) and np.all(np.isfinite(to_np(mr)))
+
+
+def test_sections_at_scale_equal_direct_section_solves(g, ctx):
+    """A larger regional survey (30 x 54 x 10 cells, 3,000 stations, four
+    sections): every section's block of the combined model equals, bitwise,
+    grav_invert run directly on that section's sub-mesh and stations after
+    grav_trend_surface removed the section's own data trend, and the detrended
+    model equals the combined model minus grav_trend_surface fitted per layer
+    over the cell centres (GPU against GPU: the same kernels run in the same
+    order, a property that holds at any size)."""
+    import torch
+    p = workloads.regional_sections(seed=46, nx=30, ny=54, nz=10, n_obs=3000, cell=50.0, nsec=4)
+    mesh = g.DeviceMesh.from_mesh(p.mesh)
+    obs = g.DeviceObs.from_survey(p.obs)
+    # data: the regional field plus two Gaussian anomalies (1 mGal, 300-500 m
+    # wide) and 1 % noise; any data serve a property that holds for all data
+    wx, wy = p.mesh.xn[-1], p.mesh.yn[-1]
+    bump = (1e-5 * np.exp(-((p.obs.x - 0.3 * wx) ** 2 + (p.obs.y - 0.45 * wy) ** 2) / 300.0 ** 2)
+            - 0.6e-5 * np.exp(-((p.obs.x - 0.7 * wx) ** 2 + (p.obs.y - 0.6 * wy) ** 2) / 500.0 ** 2))
+    d_np = inversion.add_noise(bump + workloads.regional_field(p), p.noise_draws, p.noise_level)
+    ysplit = [int(j) for j in p.extra["ysplit"]]
+    kw = dict(lam=-1.0, tol=1e-8, max_iter=3000, prec=g.GRAV_MIXED)
+    m, mr, info = ctx.invert_sections(mesh, obs, _t(d_np), _t(p.wdepth), ysplit, data_degree=2,
+                                      data_scope="section", model_degree=2, **kw)
+    m, mr = to_np(m), to_np(mr)
+    sec = sections.section_of_stations(p.mesh, p.obs, ysplit)
+    for s in range(len(ysplit) - 1):
+        j0, j1 = ysplit[s], ysplit[s + 1]
+        rows = np.flatnonzero(sec == s)
+        so = p.obs.take(rows)
+        sm = sections.sub_mesh(p.mesh, j0, j1)
+        cells = sections.cell_slice(p.mesh, j0, j1)
+        smesh, sobs = g.DeviceMesh.from_mesh(sm), g.DeviceObs.from_survey(so)
+        ds = _t(d_np[rows])
+        ctx.trend_surface(sobs.x, sobs.y, ds, degree=2, resid=ds)
+        ms, _, inf = ctx.invert(smesh, sobs, ds, _t(p.wdepth[cells]), **kw)
+        print(f"[sections] scale: section {s}: {so.n} stations, {inf['iters']} iterations", flush=True)
+        assert info[s]["iters"] == inf["iters"]
+        assert np.array_equal(m[cells], to_np(ms)), f"section {s}"
+    xc, yc, _ = workloads.cell_centres(p.mesh)
+    X, Y = np.meshgrid(xc, yc, indexing="ij")
+    Xd, Yd = _t(X.reshape(-1)), _t(Y.reshape(-1))
+    m3 = m.reshape(p.mesh.shape)
+    for k in range(p.mesh.nz):
+        layer = _t(m3[:, :, k].reshape(-1))
+        ctx.trend_surface(Xd, Yd, layer, degree=2, resid=layer)
+        assert np.array_equal(mr.reshape(p.mesh.shape)[:, :, k].reshape(-1), to_np(layer)), k
+    torch.cuda.synchronize()
