@@ -136,7 +136,8 @@ const char *grav_last_error(const grav_ctx *ctx);
 /* Device workspace bytes that `op` needs for this shape and precision (K =
  * models for GRAV_OP_FORWARD_MULTI, ignored otherwise; GRAV_OP_TREND ignores
  * nx, ny, nz, n and prec).  Host-only; 0 means the shape or combination is
- * invalid. */
+ * invalid.  The figure for n observations also covers every survey of fewer
+ * observations on the same mesh. */
 uint64_t grav_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int64_t n, grav_op op,
                               grav_prec prec, int32_t K);
 
@@ -296,7 +297,8 @@ typedef struct {
  * sections finished before it): GRAV_EINVAL also for a section without
  * stations, fewer stations (or horizontal cells) than a trend surface needs,
  * or points that do not determine it; GRAV_ENOMEM below
- * grav_workspace_bytes(.., GRAV_OP_SECTIONS, ..), which bounds any split. */
+ * grav_workspace_bytes(.., GRAV_OP_SECTIONS, ..), which bounds every split
+ * of that mesh and survey. */
 int grav_invert_sections(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs,
                          const double *d_obs, const double *wdepth, double lambda,
                          const grav_cg_opts *cg, const grav_section_opts *sec, double *m_out,
@@ -326,7 +328,7 @@ int grav_forward_multi(grav_ctx *ctx, const grav_mesh *mesh, const grav_obs *obs
  *   frees nothing (no hipMalloc/hipFree, no allocating library call).
  *   Problems whose forward workspace (grav_workspace_bytes(.., GRAV_OP_FORWARD,
  *   ..) plus 16 KiB) exceeds it are rejected with GRAV_ENOMEM before any work
- *   is enqueued (the paper-scale 178,797 x 3,307,500 forward needs 91 MiB).
+ *   is enqueued (the paper-scale 178,797 x 3,307,500 forward needs 101 MiB).
  *   validate != 0: the arguments are checked on the device first and the call
  *   waits for that check on `stream` (as with a validating context); 0: the
  *   call is fully asynchronous and the caller guarantees the preconditions.

@@ -94,6 +94,12 @@ AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n, int64_t target_waves 
                          int64_t max_partial_bytes = 0);
 NodeAdjointPlan plan_adjoint_nodes(int64_t nnodes, int64_t n);
 ForwardPlan plan_trace(int nx, int64_t n);
+// Workspace bounds: the largest partial buffers (doubles, or part counts) the
+// plans above make for any survey of at most n observations.
+int64_t forward_partials_bound(int64_t ncols, int64_t n);
+int64_t trace_partials_bound(int nx, int64_t n);
+int64_t adjoint_parts_bound(int64_t ncols, int nz, int64_t n);
+int64_t node_adjoint_parts_bound(int64_t nnodes, int64_t n);
 
 // ---- launchers (enqueue on `st`; return hipSuccess or the launch error) ---
 

@@ -378,7 +378,13 @@ uint64_t multi_workspace_need(const Mesh &g, int64_t n, grav_prec prec, int K) {
         c.take<float>(packed);
     }
     c.take<float>(g.nz + 1);
-    c.take<double>((size_t)mp.nchunk * n * kModels);
+    // chunks x n for every survey of at most n observations: a chunk count
+    // rounded up to a multiple of 8 is below 4096 / tiles + 8, and tiles >=
+    // n / kTileObs, so chunks x n stays below 4096 kTileObs + 8 n
+    int64_t cn = (mp.nblk > 0 ? mp.nblk : 1) * n;
+    const int64_t cn_round = 4096 * (int64_t)kTileObs + 8 * n;
+    if (cn_round < cn) cn = cn_round;
+    c.take<double>((size_t)cn * kModels);
     return c.off;
 }
 

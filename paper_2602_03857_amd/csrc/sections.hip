@@ -162,12 +162,19 @@ static void take_sections_head(Counter &c, const Mesh &g, int64_t n) {
     for (int i = 0; i < 3; ++i) c.take<double>(ncol);   // X Y layer
 }
 
+// The section solves need at most the largest inversion workspace over every
+// section width (1 .. ny cell rows) with all n stations: a narrower section
+// can split its stations into more parts than a wider one, so the whole
+// problem's own need is not a bound.
 uint64_t sections_workspace_need(const Mesh &g, int64_t n, grav_prec prec) {
     Counter c;
     take_sections_head(c, g, n);
-    const size_t inner_inv = workspace_need(g.nx, g.ny, g.nz, n, GRAV_OP_INVERT, prec, 0);
-    const size_t inner_tr = trend_workspace_need();
-    return c.off + (inner_inv > inner_tr ? inner_inv : inner_tr);
+    size_t inner = trend_workspace_need();
+    for (int nys = 1; nys <= g.ny; ++nys) {
+        const size_t inv = workspace_need(g.nx, nys, g.nz, n, GRAV_OP_INVERT, prec, 0);
+        if (inv > inner) inner = inv;
+    }
+    return c.off + inner;
 }
 
 int run_sections(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,

@@ -261,8 +261,7 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
 
 static size_t need_forward(const Mesh &g, int64_t n, grav_prec prec) {
     Counter c;
-    const ForwardPlan fp = plan_forward(g.ncols(), n);
-    c.take<double>((size_t)fp.nchunk * n);
+    c.take<double>((size_t)forward_partials_bound(g.ncols(), n));
     if (prec == GRAV_MIXED) {
         c.take<float>(layer_table_len(g.nz));
         c.take<double>(g.nsegs());
@@ -275,13 +274,11 @@ static size_t need_forward(const Mesh &g, int64_t n, grav_prec prec) {
 static size_t need_adjoint(const Mesh &g, int64_t n, grav_prec prec) {
     Counter c;
     if (prec == GRAV_MIXED) {
-        const AdjointPlan ap = plan_adjoint(g.ncols(), g.nz, n);
         c.take<float>(layer_table_len(g.nz));
-        c.take<double>((size_t)ap.nparts * g.nsegs());
+        c.take<double>((size_t)adjoint_parts_bound(g.ncols(), g.nz, n) * g.nsegs());
         c.take<double>(g.nsegs());
     } else {
-        const NodeAdjointPlan ap = plan_adjoint_nodes(g.nnodes(), n);
-        c.take<double>((size_t)ap.nparts * g.nnodes());
+        c.take<double>((size_t)node_adjoint_parts_bound(g.nnodes(), n) * g.nnodes());
         c.take<double>(g.nnodes());
     }
     return c.off;
@@ -289,8 +286,7 @@ static size_t need_adjoint(const Mesh &g, int64_t n, grav_prec prec) {
 
 static size_t need_trace(const Mesh &g, int64_t n) {
     Counter c;
-    const ForwardPlan tp = plan_trace(g.nx, n);
-    c.take<double>((size_t)tp.nchunk * n);
+    c.take<double>((size_t)trace_partials_bound(g.nx, n));
     c.take<double>(n);
     c.take<float>(layer_table_len(g.nz));
     return c.off;

@@ -492,6 +492,40 @@ NodeAdjointPlan plan_adjoint_nodes(int64_t nnodes, int64_t n) {
     return p;
 }
 
+// Upper bounds on the partial-sum buffers above over every survey of at most
+// n observations, so that a workspace sized for n serves any smaller survey
+// (the plans round counts up to a multiple of 8, which alone is not monotone
+// in n).  A chunk count rounded up to a multiple of 8 is below T / w + 8 for
+// w = ceil(n' / 64) >= n' / 64 waves, so chunks x n' < 64 T + 8 n'; part
+// counts requested for n bound the (monotone) requests of every n' <= n.
+int64_t forward_partials_bound(int64_t ncols, int64_t n) {
+    int64_t cap = ncols / kMinColsPerChunk;
+    if (cap < 1) cap = 1;
+    const int64_t a = cap * n, b = 64 * kTargetWavesFwd + 8 * n;
+    return a < b ? a : b;
+}
+
+int64_t trace_partials_bound(int nx, int64_t n) {
+    const int64_t a = (int64_t)(nx < 1 ? 1 : nx) * n, b = 64 * kTargetWavesFwd + 8 * n;
+    return a < b ? a : b;
+}
+
+int64_t adjoint_parts_bound(int64_t ncols, int nz, int64_t n) {
+    const int64_t waves = ceil_div(ncols, kBlock) * ceil_div(nz, kAdjLayers) * (kBlock / 64);
+    int64_t cap = n / kMinObsPerPart;
+    const int64_t mem_cap = kMaxPartialBytes / (ncols * nz * 8);
+    if (mem_cap < cap) cap = mem_cap;
+    return round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
+}
+
+int64_t node_adjoint_parts_bound(int64_t nnodes, int64_t n) {
+    const int64_t waves = ceil_div(nnodes, kBlock) * (kBlock / 64);
+    int64_t cap = n / kMinObsPerPart;
+    const int64_t mem_cap = kMaxPartialBytes / (nnodes * 8);
+    if (mem_cap < cap) cap = mem_cap;
+    return round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_layer_thickness(const Mesh &g, float *hk, hipStream_t st) {

@@ -53,6 +53,31 @@ def test_workspace_query_is_host_only_and_sane():
     assert g.workspace_bytes(4, 4, 4, 10, g.OP_DATASPACE, g.GRAV_FP64) > 0
 
 
+def test_workspace_query_bounds_every_smaller_problem():
+    """A workspace sized for n stations serves every survey of at most n
+    stations (the plans round chunk and part counts up to a multiple of 8,
+    which alone is not monotone in n), and the section query bounds the
+    inversion of every section width with any share of the stations."""
+    import random
+    g = load_package()
+    rng = random.Random(7)
+    ops = (g.OP_FORWARD, g.OP_ADJOINT, g.OP_DATASPACE, g.OP_TRACE, g.OP_INVERT)
+    for nx, ny, nz, n in ((10, 18, 6, 320), (40, 200, 20, 50_000), (150, 150, 147, 178_797)):
+        for prec in (g.GRAV_MIXED, g.GRAV_FP64):
+            full = {op: g.workspace_bytes(nx, ny, nz, n, op, prec) for op in ops}
+            sec = g.workspace_bytes(nx, ny, nz, n, g.OP_SECTIONS, prec)
+            for _ in range(400):
+                nn = rng.randint(1, n)
+                for op in ops:
+                    assert g.workspace_bytes(nx, ny, nz, nn, op, prec) <= full[op], (op, nn)
+                if prec == g.GRAV_MIXED:
+                    for K in (16, 64):
+                        assert (g.workspace_bytes(nx, ny, nz, nn, g.OP_FORWARD_MULTI, g.GRAV_MIXED_BF16X3, K)
+                                <= g.workspace_bytes(nx, ny, nz, n, g.OP_FORWARD_MULTI, g.GRAV_MIXED_BF16X3, K))
+                nys = rng.randint(1, ny)
+                assert g.workspace_bytes(nx, nys, nz, nn, g.OP_INVERT, prec) < sec, (nys, nn)
+
+
 def test_context_creation_reports_missing_device_or_succeeds():
     g = load_package()
     import torch
