@@ -2,15 +2,16 @@
 // K <= 64 density models): a dense contraction over prisms, so it runs on
 // the matrix cores.
 //
-// Per workgroup: 64 observations x all 64 (padded) models, looping over
-// blocks of kPBX x kPBY prism columns and, inside each, over the layers.  One
-// layer step of one block:
-//   1. VALU: edge-segment terms S for the (kPBX+1) x (kPBY+1) vertical edges
-//      around the block's prisms, for the 64 observations (z-carry of R along
-//      each edge) -> LDS.  A 4 x 4 block's 25 edge terms serve 16 prisms
-//      (1.56 per prism).  Larger blocks need fewer (8 x 4: 1.41), but their
-//      register and LDS footprint cost occupancy, and at 500,000 prisms x
-//      64 models they were measured no faster.
+// Per workgroup: 64 observations x all 64 (padded) models and one chunk of
+// consecutive kPBX x kPBY prism-column blocks; the layers are the outer loop
+// and the chunk's blocks the inner one.  One block step (one layer of one
+// block):
+//   1. VALU: edge-segment terms S of the block's vertical edges for the 64
+//      observations -> LDS.  Consecutive blocks along y share an edge row, and
+//      the LDS rows form a ring, so a step evaluates only the (kPBX+1) x kPBY
+//      new edges: 20 for the 16 prisms of a 4 x 4 block (1.25 per prism,
+//      five per wave), all 25 at the start of a chunk or a block row.  Both
+//      end nodes of each segment are formed in the step.
 //   2. VALU: per prism G = S00 - S10 - S01 + S11 (the (x, y) vertex parity of
 //      Eq. 1), split into bf16 hi = bf16(G), lo = bf16(G - hi) -> LDS in the
 //      MFMA A-operand order (obs x prisms).
@@ -18,13 +19,13 @@
 //      acc += A_hi B_hi + A_hi B_lo + A_lo B_hi with v_mfma_f32_32x32x16_bf16
 //      (FP32 accumulation), 16 prisms per instruction, B = the models
 //      pre-split into bf16 hi/lo and packed so that each lane loads its 8
-//      operands with one 16-byte load; the next step's B operands are loaded
-//      while this step's edge terms are computed.
-// After each prism-column block the FP32 MFMA accumulators are added into
-// per-thread FP64 accumulators (four in registers, twelve in LDS: 128 VGPRs
-// and 35 KB of LDS allow four waves per SIMD), so FP32 accumulates the terms
-// of one block only.  The GRAV_FP32_VALU variant keeps steps 1-2 (G in FP32) and
-// contracts on the vector ALUs.
+//      operands with one 16-byte load; the step's B operands are loaded
+//      while its edge terms are computed.
+// Every kFlushBlocks block steps and at the end of each layer the FP32
+// accumulators are added into per-thread FP64 accumulators (four in
+// registers, twelve in LDS), so FP32 sums at most 512 prism terms.  The
+// GRAV_FP32_VALU variant keeps steps 1-2 (G in FP32) and contracts on the
+// vector ALUs.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -46,8 +47,6 @@ constexpr int kTileObs = 64;
 constexpr int kPBX = GRAV_MULTI_PBX;                     // prism columns per block along x
 constexpr int kPBY = GRAV_MULTI_PBY;                     // ... along y
 constexpr int kEdgeX = kPBX + 1, kEdgeY = kPBY + 1;
-constexpr int kEdgeCols = kEdgeX * kEdgeY;               // edge columns per block
-constexpr int kColsPerWave = (kEdgeCols + 3) / 4;        // wave w takes w, w+4, ...
 constexpr int kPrismsPerStep = kPBX * kPBY;              // prisms per layer step
 constexpr int kKSteps = kPrismsPerStep / 16;             // MFMA K = 16 per instruction
 constexpr int kModels = 64;
@@ -114,6 +113,11 @@ __device__ __forceinline__ double &acc_ref(double (&r)[kRegAcc > 0 ? kRegAcc : 1
     return v < kRegAcc ? r[v] : lds[v - kRegAcc][t];
 }
 
+// The FP32 accumulators (MFMA or VALU) are added into the FP64 ones after
+// this many block steps and at the end of every layer, so an FP32 sum holds at
+// most kFlushBlocks * kPrismsPerStep prism terms.
+constexpr int kFlushBlocks = 32;
+
 template <bool kMfma>
 __global__ __launch_bounds__(256) void k_forward_multi(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
@@ -122,7 +126,10 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     const __bf16 *__restrict__ bhi, const __bf16 *__restrict__ blo,
     const float *__restrict__ b32, int nby, int64_t nblk, int64_t blocks_per_chunk, int nchunk,
     double *__restrict__ partial) {
-    __shared__ float sS[kEdgeCols][kTileObs];
+    // edge terms of the current block step: [y slot][x edge][observation]; the
+    // y slots form a ring, so the last edge row of one block is the first of
+    // the next block along y without being copied
+    __shared__ float sS[kEdgeY][kEdgeX][kTileObs];
     __shared__ __attribute__((aligned(16))) __bf16 sAhi[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) __bf16 sAlo[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sA32[kTileObs][kPrismsPerStep];
@@ -141,7 +148,6 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     const int64_t o = tile * kTileObs + lo_;
     const int64_t oc = o < n ? o : n - 1;
     const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
-    const float ztop = static_cast<float>(zn[0] - zo);
     const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
     const int64_t b0 = (int64_t)chunk * blocks_per_chunk;
     const int64_t b1 = b0 + blocks_per_chunk < nblk ? b0 + blocks_per_chunk : nblk;
@@ -156,25 +162,39 @@ __global__ __launch_bounds__(256) void k_forward_multi(
         acc32[v] = 0.0f;
         acc_ref(rAcc, sAcc, v, t) = 0.0;
     }
-
-    for (int64_t blk = b0; blk < b1; ++blk) {
-        const int i0 = (int)(blk / nby) * kPBX;
-        const int j0 = (int)(blk % nby) * kPBY;
-        float cx[kColsPerWave], cy[kColsPerWave], cR[kColsPerWave];
-        bool valid[kColsPerWave];
+    auto flush = [&]() {
 #pragma unroll
-        for (int u = 0; u < kColsPerWave; ++u) {
-            const int c = wv + 4 * u;
-            const int a = i0 + c / kEdgeY, b = j0 + c % kEdgeY;
-            valid[u] = c < kEdgeCols && a <= nx && b <= ny;
-            const int ac = a <= nx ? a : nx, bc = b <= ny ? b : ny;
-            cx[u] = column_offset(xn[ac], xo);
-            cy[u] = column_offset(yn[bc], yo);
-            const Column col = column_from_xy(cx[u], cy[u]);
-            cR[u] = make_node(col, ztop).R;
+        for (int v = 0; v < 16; ++v) {
+            if (kMfma) {
+                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc[v]);
+                acc[v] = 0.0f;
+            } else {
+                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc32[v]);
+                acc32[v] = 0.0f;
+            }
         }
-        float zt = ztop, zzt = ztop * ztop;
-        for (int k = 0; k < nz; ++k) {
+    };
+
+    // Layers outside, the chunk's prism-column blocks inside: consecutive
+    // blocks along y share an edge row, so a block step evaluates the
+    // kEdgeX x kPBY new edges only (4 x 4 block: 20 edge terms for 16 prisms,
+    // 1.25 per prism, five per wave), and the full kEdgeX x kEdgeY at the
+    // start of a chunk or of a block row.  Both end nodes of a segment are
+    // formed here (no carry along z across block steps).
+    for (int k = 0; k < nz; ++k) {
+        const float zt = static_cast<float>(zn[k] - zo);
+        const float zb = static_cast<float>(zn[k + 1] - zo);
+        const float h = hk[k];
+        const bool deep = k >= kdeep;   // uniform: deep layers take the shorter formula
+        int slot0 = 0;                  // ring slot of the block's first edge row
+        int nacc = 0;
+        float cxr[kEdgeX];              // x offsets of the current block row's edges
+        bool vx[kEdgeX];
+        for (int64_t blk = b0; blk < b1; ++blk) {
+            const int bi = (int)(blk / nby);
+            const int bj = (int)(blk - (int64_t)bi * nby);
+            const int i0 = bi * kPBX, j0 = bj * kPBY;
+            const bool fresh = blk == b0 || bj == 0;
             // this step's model operands, loaded while the edge terms compute
             bf16x8 bh[kKSteps], bl[kKSteps];
             if (kMfma) {
@@ -187,45 +207,52 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                     bl[kk] = *reinterpret_cast<const bf16x8 *>(blo + bo + 16 * kk);
                 }
             }
-            const float zb = static_cast<float>(zn[k + 1] - zo);
-            const float h = hk[k];
-            // phase 1: edge terms of this layer (deep layers, as in the
-            // single-model sweeps, take the shorter formula; k is uniform)
-            auto edge_terms = [&](auto deep) {
-                constexpr bool kDeep = decltype(deep)::value;
+            if (fresh) {
+                slot0 = 0;
 #pragma unroll
-                for (int u = 0; u < kColsPerWave; ++u) {
-                    const int c = wv + 4 * u;
-                    if (c < kEdgeCols) {
-                        // recompute the column terms each layer rather than keeping
-                        // those of all the wave's columns live across the layer loop
-                        float xu = cx[u], yu = cy[u];
-                        asm volatile("" : "+v"(xu), "+v"(yu));
-                        const Column col = column_from_xy(xu, yu);
-                        Node top;
-                        top.z = zt;
-                        top.zz = zzt;
-                        top.R = cR[u];
-                        top.zR = zt * cR[u];
+                for (int ii = 0; ii < kEdgeX; ++ii) {
+                    const int a = i0 + ii;
+                    vx[ii] = a <= nx;
+                    cxr[ii] = column_offset(xn[a <= nx ? a : nx], xo);
+                }
+            } else {
+                slot0 += kPBY;
+                if (slot0 >= kEdgeY) slot0 -= kEdgeY;
+            }
+            // phase 1: edge terms S of edge row q (y node j0 + q) at the x
+            // edges ii with (ii mod 4) == wv, or at all of them
+            auto edge_row = [&](auto deepc, int q, bool all_x) {
+                constexpr bool kDeep = decltype(deepc)::value;
+                const int b = j0 + q;
+                const bool vy = b <= ny;
+                const float cy = column_offset(yn[vy ? b : ny], yo);
+                int slot = slot0 + q;
+                if (slot >= kEdgeY) slot -= kEdgeY;
+#pragma unroll
+                for (int ii = 0; ii < kEdgeX; ++ii) {
+                    if (all_x || (ii & 3) == wv) {
+                        const Column col = column_from_xy(cxr[ii], cy);
+                        const Node top = make_node(col, zt);
                         const Node bot = make_node(col, zb);
                         const float S = edge_segment<kDeep>(col, top, bot, h);
-                        sS[c][lo_] = valid[u] ? S : 0.0f;
-                        cR[u] = bot.R;
+                        sS[slot][ii][lo_] = (vx[ii] && vy) ? S : 0.0f;
                     }
                 }
             };
-            if (k >= kdeep)
-                edge_terms(std::true_type{});
+            auto phase1 = [&](auto deepc) {
+                // wave wv owns the new edge row q = wv + 1 (kPBY == 4 waves)
+                edge_row(deepc, wv + 1, true);
+                if (fresh) edge_row(deepc, 0, false);
+            };
+            if (deep)
+                phase1(std::true_type{});
             else
-                edge_terms(std::false_type{});
-            zt = zb;
-            zzt = zb * zb;
+                phase1(std::false_type{});
             __syncthreads();
             // phase 2: prism terms of prism rows ii = wv, wv + 4, ... (all jj)
-            // for observation lo_
-            // A row's kPBY prisms are stored with one vector write per array
-            // (scattered 2-byte writes to rows 32 bytes apart conflict on the
-            // LDS banks).
+            // for observation lo_.  A row's kPBY prisms are stored with one
+            // vector write per array (scattered 2-byte writes to rows 32 bytes
+            // apart conflict on the LDS banks).
 #pragma unroll
             for (int r = 0; r < kPBX / 4; ++r) {
                 const int ii = wv + 4 * r;
@@ -233,9 +260,11 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                 float g4[kPBY];
 #pragma unroll
                 for (int q = 0; q < kPBY; ++q) {
-                    const int e = ii * kEdgeY + q;
-                    float G = (sS[e][lo_] - sS[e + kEdgeY][lo_]) -
-                              (sS[e + 1][lo_] - sS[e + kEdgeY + 1][lo_]);
+                    int s0 = slot0 + q;
+                    if (s0 >= kEdgeY) s0 -= kEdgeY;
+                    const int s1 = s0 + 1 < kEdgeY ? s0 + 1 : 0;
+                    float G = (sS[s0][ii][lo_] - sS[s0][ii + 1][lo_]) -
+                              (sS[s1][ii][lo_] - sS[s1][ii + 1][lo_]);
                     G = (i0 + ii < nx && j0 + q < ny) ? G : 0.0f;
                     g4[q] = G;
                     hi4[q] = static_cast<__bf16>(G);
@@ -276,17 +305,12 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                     for (int v = 0; v < 16; ++v) acc32[v] = fmaf(gp, sB32[p][wv * 16 + v], acc32[v]);
                 }
             }
-        }
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            if (kMfma) {
-                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc[v]);
-                acc[v] = 0.0f;
-            } else {
-                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc32[v]);
-                acc32[v] = 0.0f;
+            if (++nacc == kFlushBlocks) {
+                flush();
+                nacc = 0;
             }
         }
+        if (nacc > 0) flush();
     }
 
     if (kMfma) {

@@ -584,6 +584,26 @@ def test_forward_multi_per_model(g, ctx, prec_name, case):
     assert np.all(errs <= TOL_MULTI)
 
 
+def test_forward_multi_chunks_of_several_blocks(g, ctx):
+    """Enough observations (33,000) that each chunk of the prism-column blocks
+    holds several blocks, so consecutive blocks share an edge row; the mesh is
+    ragged in x and y (18 x 15 cells: partial blocks) and chunks start in the
+    middle of a block row.  200 seeded rows per model against the oracle."""
+    import torch
+    p = workloads.random_case(24, 18, 15, 7, 33_000, on_top=40, on_nodes=20)
+    models = _blocky_models(p.mesh, 7, 24)
+    rows = np.sort(np.random.default_rng(24).choice(p.obs.n, 200, replace=False))
+    ref = prism.forward_multi(p.mesh, p.obs, models.astype(np.float64), rows=rows)
+    mesh, obs = _dev(g, p)
+    mt = torch.as_tensor(models, device="cuda")
+    for prec_name in ("GRAV_MIXED_BF16X3", "GRAV_FP32_VALU"):
+        D = to_np(ctx.forward_multi(mesh, obs, mt, prec=getattr(g, prec_name)))[rows]
+        errs = np.linalg.norm(D - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        print(f"[parity] multi chunks of several blocks {prec_name}: per-model rel L2 max "
+              f"{errs.max():.2e} median {np.median(errs):.2e}", flush=True)
+        assert np.all(errs <= TOL_MULTI)
+
+
 def test_forward_multi_box_models_sampled_rows(g, ctx):
     """64 models on the 500k-cell mesh with 10,000 observations; 48 seeded rows
     per model against the FP64 oracle, for both contraction paths."""
