@@ -19,8 +19,7 @@
 //      acc += A_hi B_hi + A_hi B_lo + A_lo B_hi with v_mfma_f32_32x32x16_bf16
 //      (FP32 accumulation), 16 prisms per instruction, B = the models
 //      pre-split into bf16 hi/lo and packed so that each lane loads its 8
-//      operands with one 16-byte load; the step's B operands are loaded
-//      while its edge terms are computed.
+//      operands with one 16-byte load, issued after step 2.
 // Every kFlushBlocks block steps and at the end of each layer the FP32
 // accumulators are added into per-thread FP64 accumulators (four in
 // registers, twelve in LDS), so FP32 sums at most 512 prism terms.  The
@@ -196,17 +195,6 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             const int i0 = bi * kPBX, j0 = bj * kPBY;
             const bool fresh = blk == b0 || bj == 0;
             // this step's model operands, loaded while the edge terms compute
-            bf16x8 bh[kKSteps], bl[kKSteps];
-            if (kMfma) {
-                const int l = lo_;
-                const int64_t bo =
-                    ((blk * nz + k) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
-#pragma unroll
-                for (int kk = 0; kk < kKSteps; ++kk) {
-                    bh[kk] = *reinterpret_cast<const bf16x8 *>(bhi + bo + 16 * kk);
-                    bl[kk] = *reinterpret_cast<const bf16x8 *>(blo + bo + 16 * kk);
-                }
-            }
             if (fresh) {
                 slot0 = 0;
 #pragma unroll
@@ -283,6 +271,20 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                     b32 + ((blk * nz + k) * kPrismsPerStep) * kModels);
                 for (int q = t; q < kPrismsPerStep * kModels / 4; q += 256)
                     reinterpret_cast<float4 *>(&sB32[0][0])[q] = src[q];
+            }
+            // this step's model operands: loaded here, after the edge and
+            // prism terms, they wait at the barrier instead of holding eight
+            // registers through phase 1
+            bf16x8 bh[kKSteps], bl[kKSteps];
+            if (kMfma) {
+                const int l = lo_;
+                const int64_t bo =
+                    ((blk * nz + k) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
+#pragma unroll
+                for (int kk = 0; kk < kKSteps; ++kk) {
+                    bh[kk] = *reinterpret_cast<const bf16x8 *>(bhi + bo + 16 * kk);
+                    bl[kk] = *reinterpret_cast<const bf16x8 *>(blo + bo + 16 * kk);
+                }
             }
             __syncthreads();
             // phase 3: contraction over the prisms of this step
