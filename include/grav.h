@@ -350,9 +350,10 @@ int grav_forward_static(const grav_mesh *mesh, const grav_obs *obs, const double
  * (one step each) in arrival order on `max_active` slots of their own, passing
  * inversions that wait only for an inversion slot (never one that waits for
  * pool memory, so no request starves).  Every scheduling step issues one
- * batched launch per sweep type that covers the blocks of all active
- * requests, so each active inversion advances one CG iteration per step and
- * requests that arrive meanwhile join at the next step.  A request's launch
+ * persistent launch per sweep type: a grid of as many waves as the GPU holds
+ * drains the tiles of all active requests (longest tiles first) from a
+ * device counter, so each active inversion advances one CG iteration per step
+ * and requests that arrive meanwhile join at the next step.  A request's launch
  * plan depends only on its own shape, so its result is bitwise the same alone
  * and in any mix.  A forward request is bitwise the same as grav_forward
  * (GRAV_MIXED).  An inversion's adjoint splits the observations into fewer

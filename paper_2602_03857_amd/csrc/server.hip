@@ -18,12 +18,15 @@
 //   sync    one copy of the CG scalar table, then the host advances each
 //           request (converged / max_iter -> final step; final -> done).
 //
-// A batched launch covers the blocks of every request in one grid: block b
-// finds its request in a table of per-request jobs (each with its own plan and
-// buffers, blocks numbered consecutively) and runs the same per-block body as
-// the single-call kernels, so a request's arithmetic does not depend on what
-// it is batched with, and the hardware dispatcher balances blocks of uneven
-// cost across the GPU.
+// A batched sweep is a persistent launch: a grid of as many waves as fit on
+// the GPU at once drains the tiles (virtual blocks, taken half a tile per wave)
+// of every request from one device counter.  A tile finds its request in a
+// table of per-request jobs
+// (each with its own plan and buffers, tiles numbered consecutively) and runs
+// the same per-block body as the single-call kernels, so a request's
+// arithmetic does not depend on what it is batched with or which block runs
+// it.  The table lists the requests by decreasing tile cost, so the longest
+// tiles are taken first and the last ones to finish are the shortest.
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -59,8 +62,6 @@ constexpr int kTraceSlot = 7;        // trace(G C G^T) when computed
 // single call to fill the GPU, and its partial sums stay small in the pool.
 constexpr int64_t kServerTargetWavesAdj = 32768;
 constexpr int64_t kServerMaxPartialBytes = int64_t(512) << 20;
-// Largest grid of one batched launch (a larger batch is split over launches).
-constexpr int64_t kMaxGridBlocks = int64_t(1) << 30;
 
 struct FwdJob {
     const double *xn, *yn, *zn, *ox, *oy, *oz, *w2;
@@ -92,33 +93,52 @@ __device__ __forceinline__ int find_job(const Job *__restrict__ jobs, int njobs,
     return lo;
 }
 
-// One block per virtual block of the batch: the block finds its request in the
-// job table and runs the same per-block body as the single-call kernel.
-__global__ __launch_bounds__(kBlock) void k_forward_batched(const FwdJob *__restrict__ jobs, int njobs,
-                                                            int64_t base) {
-    const int64_t vb = base + blockIdx.x;
-    const FwdJob &j = jobs[find_job(jobs, njobs, vb)];
-    const int64_t local = vb - j.block_begin;
-    forward_mixed_block(global_ptr(j.xn), global_ptr(j.yn), global_ptr(j.zn), j.ny1, j.nz,
-                        global_ptr(j.hk), global_ptr(j.ox), global_ptr(j.oy), global_ptr(j.oz), j.n,
-                        global_ptr(j.w2), j.ncols, j.cols_per_chunk, (int)(local % j.nchunk),
-                        local / j.nchunk, global_ptr(j.partial));
+// Persistent launches drain half tiles: a tile is a kBlock-lane block of the
+// single-call plan, and each wave (one 64-thread block) takes the next half
+// tile from a device counter (one atomic add by lane 0, made wave-uniform with
+// readfirstlane) and runs its 64 lanes of that block's body, with no barrier
+// and no shared memory.  The counter only grows, so every wave leaves its
+// loop once the counter has passed the number of half tiles.
+__device__ __forceinline__ uint32_t next_half_tile(uint32_t *next) {
+    uint32_t v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(next, 1u);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+constexpr int kHalves = kBlock / 64;   // waves per tile
+
+__global__ __launch_bounds__(64) void k_forward_batched(const FwdJob *__restrict__ jobs, int njobs,
+                                                        uint32_t halves, uint32_t *__restrict__ next) {
+    for (uint32_t hv = next_half_tile(next); hv < halves; hv = next_half_tile(next)) {
+        const int64_t vb = hv / kHalves;
+        const int lane = (int)(hv % kHalves) * 64 + (int)threadIdx.x;
+        const FwdJob &j = jobs[find_job(jobs, njobs, vb)];
+        const int64_t local = vb - j.block_begin;
+        forward_mixed_block(global_ptr(j.xn), global_ptr(j.yn), global_ptr(j.zn), j.ny1, j.nz,
+                            global_ptr(j.hk), global_ptr(j.ox), global_ptr(j.oy), global_ptr(j.oz), j.n,
+                            global_ptr(j.w2), j.ncols, j.cols_per_chunk, (int)(local % j.nchunk),
+                            local / j.nchunk, global_ptr(j.partial), lane);
+    }
 }
 
 // Bounded to 8 waves per SIMD like the single-call adjoint sweep.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void k_adjoint_batched(const AdjJob *__restrict__ jobs, int njobs, int64_t base) {
-    const int64_t vb = base + blockIdx.x;
-    const AdjJob &j = jobs[find_job(jobs, njobs, vb)];
-    int64_t local = vb - j.block_begin;
-    const int part = (int)(local % j.nparts);
-    local /= j.nparts;
-    const int kc = (int)(local % j.nkc);
-    local /= j.nkc;
-    adjoint_mixed_block(global_ptr(j.xn), global_ptr(j.yn), global_ptr(j.zn), j.ny1, j.nz,
-                        global_ptr(j.hk), global_ptr(j.ox), global_ptr(j.oy), global_ptr(j.oz),
-                        global_ptr(j.v), j.n, j.obs_per_part, j.ncols, j.nkc, part, kc, local,
-                        global_ptr(j.upart));
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_adjoint_batched(const AdjJob *__restrict__ jobs, int njobs, uint32_t halves,
+                       uint32_t *__restrict__ next) {
+    for (uint32_t hv = next_half_tile(next); hv < halves; hv = next_half_tile(next)) {
+        const int64_t vb = hv / kHalves;
+        const int lane = (int)(hv % kHalves) * 64 + (int)threadIdx.x;
+        const AdjJob &j = jobs[find_job(jobs, njobs, vb)];
+        int64_t local = vb - j.block_begin;
+        const int part = (int)(local % j.nparts);
+        local /= j.nparts;
+        const int kc = (int)(local % j.nkc);
+        local /= j.nkc;
+        adjoint_mixed_block(global_ptr(j.xn), global_ptr(j.yn), global_ptr(j.zn), j.ny1, j.nz,
+                            global_ptr(j.hk), global_ptr(j.ox), global_ptr(j.oy), global_ptr(j.oz),
+                            global_ptr(j.v), j.n, j.obs_per_part, j.ncols, j.nkc, part, kc, local,
+                            global_ptr(j.upart), lane);
+    }
 }
 
 // scal[kLambdaSlot] = lambda >= 0 ? lambda : 1e-2 * scal[kTraceSlot] / n
@@ -217,6 +237,8 @@ struct grav_server {
     double *scal_host = nullptr;     // pinned mirror
     FwdJob *fjobs_dev = nullptr, *fjobs_host = nullptr;   // 2 max_active entries
     AdjJob *ajobs_dev = nullptr, *ajobs_host = nullptr;   // max_active entries
+    uint32_t *tile_next = nullptr;                        // [0] adjoint, [1] forward half-tile counter
+    unsigned fwd_grid = 1, adj_grid = 1;                  // resident waves of the persistent sweeps
     std::vector<int> free_inv_slots, free_fwd_slots;
     grav_ctx *vctx = nullptr;        // validation of submitted requests
     std::mutex vmu;
@@ -274,11 +296,20 @@ int grav_server::step(std::vector<Request *> &reqs) {
         STEP_TRY(launch_dot_finish(q->dpart, scal, kFinishInit, 0, st));
         q->phase = Phase::CG;
     }
-    // ---- batched adjoint sweep
+    // ---- batched adjoint sweep (requests by decreasing tile cost: observations
+    // per part x layers per chunk)
+    std::vector<Request *> order;
+    for (Request *q : reqs)
+        if (q->phase == Phase::CG || q->phase == Phase::Final) order.push_back(q);
+    auto adj_tile_cost = [](const Request *q) {
+        return q->ap.obs_per_part * (int64_t)((q->g.nz + q->ap.nkc - 1) / q->ap.nkc);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](const Request *a, const Request *b) {
+        return adj_tile_cost(a) > adj_tile_cost(b);
+    });
     int na = 0;
     int64_t atotal = 0;
-    for (Request *q : reqs) {
-        if (q->phase != Phase::CG && q->phase != Phase::Final) continue;
+    for (Request *q : order) {
         AdjJob &j = ajobs_host[na++];
         j = AdjJob{q->g.xn, q->g.yn, q->g.zn, q->o.x, q->o.y, q->o.z,
                    q->phase == Phase::CG ? q->p : q->y, q->hk, q->upart, q->o.n, q->ap.obs_per_part,
@@ -287,11 +318,11 @@ int grav_server::step(std::vector<Request *> &reqs) {
     }
     if (na) {
         STEP_TRY(hipMemcpyAsync(ajobs_dev, ajobs_host, na * sizeof(AdjJob), hipMemcpyHostToDevice, st));
-        for (int64_t base = 0; base < atotal; base += kMaxGridBlocks) {
-            const unsigned grid = (unsigned)std::min<int64_t>(atotal - base, kMaxGridBlocks);
-            k_adjoint_batched<<<grid, kBlock, 0, st>>>(ajobs_dev, na, base);
-            STEP_TRY(hipGetLastError());
-        }
+        if (atotal * kHalves > INT32_MAX) return (int)hipErrorInvalidValue;
+        STEP_TRY(hipMemsetAsync(tile_next, 0, sizeof(uint32_t), st));
+        const unsigned grid = (unsigned)std::min<int64_t>(atotal * kHalves, adj_grid);
+        k_adjoint_batched<<<grid, 64, 0, st>>>(ajobs_dev, na, (uint32_t)(atotal * kHalves), tile_next);
+        STEP_TRY(hipGetLastError());
     }
     for (Request *q : reqs) {
         if (q->phase != Phase::CG && q->phase != Phase::Final) continue;
@@ -304,12 +335,20 @@ int grav_server::step(std::vector<Request *> &reqs) {
             STEP_TRY(launch_adjoint_finish_edges(g, q->U, GRAV_GAMMA, q->r.wdepth, nullptr, q->r.m_out, st));
         }
     }
-    // ---- batched forward sweep
-    int nf = 0;
-    int64_t ftotal = 0;
+    // ---- batched forward sweep (requests by decreasing tile cost: node
+    // columns per chunk x layers)
+    order.clear();
     for (Request *q : reqs) {
         const bool fwd = q->r.kind == GRAV_REQ_FORWARD && q->phase == Phase::Init;
-        if (!fwd && q->phase != Phase::CG) continue;
+        if (fwd || q->phase == Phase::CG) order.push_back(q);
+    }
+    auto fwd_tile_cost = [](const Request *q) { return q->fp.cols_per_chunk * (int64_t)q->g.nz; };
+    std::stable_sort(order.begin(), order.end(), [&](const Request *a, const Request *b) {
+        return fwd_tile_cost(a) > fwd_tile_cost(b);
+    });
+    int nf = 0;
+    int64_t ftotal = 0;
+    for (Request *q : order) {
         FwdJob &j = fjobs_host[nf++];
         j = FwdJob{q->g.xn, q->g.yn, q->g.zn, q->o.x, q->o.y, q->o.z, q->w2, q->hk, q->fpart, q->o.n,
                    q->g.ncols(), q->fp.cols_per_chunk, ftotal, q->g.ny + 1, q->g.nz, q->fp.nchunk, 0};
@@ -317,11 +356,11 @@ int grav_server::step(std::vector<Request *> &reqs) {
     }
     if (nf) {
         STEP_TRY(hipMemcpyAsync(fjobs_dev, fjobs_host, nf * sizeof(FwdJob), hipMemcpyHostToDevice, st));
-        for (int64_t base = 0; base < ftotal; base += kMaxGridBlocks) {
-            const unsigned grid = (unsigned)std::min<int64_t>(ftotal - base, kMaxGridBlocks);
-            k_forward_batched<<<grid, kBlock, 0, st>>>(fjobs_dev, nf, base);
-            STEP_TRY(hipGetLastError());
-        }
+        if (ftotal * kHalves > INT32_MAX) return (int)hipErrorInvalidValue;
+        STEP_TRY(hipMemsetAsync(tile_next + 1, 0, sizeof(uint32_t), st));
+        const unsigned grid = (unsigned)std::min<int64_t>(ftotal * kHalves, fwd_grid);
+        k_forward_batched<<<grid, 64, 0, st>>>(fjobs_dev, nf, (uint32_t)(ftotal * kHalves), tile_next + 1);
+        STEP_TRY(hipGetLastError());
     }
     for (Request *q : reqs) {
         const int64_t n = q->o.n;
@@ -476,6 +515,18 @@ extern "C" int grav_server_create(grav_server **out, const grav_server_opts *opt
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->ajobs_dev), (size_t)s->max_active * sizeof(AdjJob));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->fjobs_host), nslots * sizeof(FwdJob), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->ajobs_host), (size_t)s->max_active * sizeof(AdjJob), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->tile_next), 2 * sizeof(uint32_t));
+    if (e == hipSuccess) {
+        // persistent grids: every wave resident at once
+        int ncu = 0, bf = 0, ba = 0;
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, k_forward_batched, 64, 0);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ba, k_adjoint_batched, 64, 0);
+        if (e == hipSuccess) {
+            s->fwd_grid = (unsigned)std::max(1, ncu * bf);
+            s->adj_grid = (unsigned)std::max(1, ncu * ba);
+        }
+    }
     if (e != hipSuccess) {
         const bool oom = e == hipErrorOutOfMemory;
         if (s->pool) (void)hipFree(s->pool);
@@ -485,6 +536,7 @@ extern "C" int grav_server_create(grav_server **out, const grav_server_opts *opt
         if (s->ajobs_dev) (void)hipFree(s->ajobs_dev);
         if (s->fjobs_host) (void)hipHostFree(s->fjobs_host);
         if (s->ajobs_host) (void)hipHostFree(s->ajobs_host);
+        if (s->tile_next) (void)hipFree(s->tile_next);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->vstream) (void)hipStreamDestroy(s->vstream);
         if (s->vevent) (void)hipEventDestroy(s->vevent);
@@ -626,6 +678,7 @@ extern "C" void grav_server_destroy(grav_server *s) {
     (void)hipFree(s->ajobs_dev);
     (void)hipHostFree(s->fjobs_host);
     (void)hipHostFree(s->ajobs_host);
+    (void)hipFree(s->tile_next);
     (void)hipStreamDestroy(s->stream);
     (void)hipStreamDestroy(s->vstream);
     (void)hipEventDestroy(s->vevent);

@@ -28,14 +28,16 @@ __device__ __forceinline__ float node_depth(const float *__restrict__ zrel, int 
 
 // Forward sweep, one block: observations oblk*kBlock + [0, kBlock) against node
 // columns [chunk*cols_per_chunk, ...), writing partial[chunk*n + o] =
-// sum over the chunk's segments of S * W2 (FP64 accumulation).
+// sum over the chunk's segments of S * W2 (FP64 accumulation).  `lane` in
+// [0, kBlock) is the calling thread's place in the block (threadIdx.x for a
+// kBlock-thread block).
 __device__ __forceinline__ void forward_mixed_block(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
     const double *__restrict__ oy, const double *__restrict__ oz, int64_t n,
     const double *__restrict__ w2, int64_t ncols, int64_t cols_per_chunk, int chunk, int64_t oblk,
-    double *__restrict__ partial) {
-    const int64_t o = oblk * kBlock + threadIdx.x;
+    double *__restrict__ partial, int lane) {
+    const int64_t o = oblk * kBlock + lane;
     const int64_t oc = o < n ? o : n - 1;
     const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
     const float ztop = static_cast<float>(zn[0] - zo);
@@ -160,14 +162,15 @@ __device__ __forceinline__ void adjoint_obs_range(
 // layer chunk kc of nkc (nkc = ceil(nz / kAdjLayers) chunks: the first
 // nz mod nkc hold one layer more than the others), observations of part
 // `part`; writes upart[part][segment] = sum_{o in part} v_o S (FP64, one
-// register pair per layer, no cross-lane reduction).
+// register pair per layer, no cross-lane reduction).  `lane` as in the forward
+// block.
 __device__ __forceinline__ void adjoint_mixed_block(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
     const double *__restrict__ oy, const double *__restrict__ oz, const double *__restrict__ v,
     int64_t n, int64_t obs_per_part, int64_t ncols, int nkc, int part, int kc, int64_t colblk,
-    double *__restrict__ upart) {
-    const int64_t col = colblk * kBlock + threadIdx.x;
+    double *__restrict__ upart, int lane) {
+    const int64_t col = colblk * kBlock + lane;
     const int64_t colc = col < ncols ? col : ncols - 1;
     int a, b;
     if (ncols <= 0x7fffffff) {   // 32-bit division when the column index fits

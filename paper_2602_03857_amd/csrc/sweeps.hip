@@ -185,7 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_mixed(
     const double *__restrict__ w2, int64_t ncols, int64_t cols_per_chunk, int nchunk,
     double *__restrict__ partial) {
     forward_mixed_block(xn, yn, zn, ny1, nz, hk, ox, oy, oz, n, w2, ncols, cols_per_chunk,
-                        (int)(blockIdx.x % nchunk), (int64_t)(blockIdx.x / nchunk), partial);
+                        (int)(blockIdx.x % nchunk), (int64_t)(blockIdx.x / nchunk), partial,
+                        (int)threadIdx.x);
 }
 
 // FP64 forward sweep over nodes: lane = observation, chunk of node columns.
@@ -236,7 +237,7 @@ void k_adjoint_mixed(
     const int kc = (int)(bid % (unsigned)nkc);
     bid /= (unsigned)nkc;
     adjoint_mixed_block(xn, yn, zn, ny1, nz, hk, ox, oy, oz, v, n, obs_per_part, ncols, nkc, part,
-                        kc, bid, upart);
+                        kc, bid, upart, (int)threadIdx.x);
 }
 
 // FP64 adjoint sweep: lane = node, P(node) = sum_{o in part} v_o Psi(node - o).
