@@ -127,8 +127,13 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     double *__restrict__ partial) {
     // edge terms of the current block step: [y slot][x edge][observation]; the
     // y slots form a ring, so the last edge row of one block is the first of
-    // the next block along y without being copied
-    __shared__ float sS[kEdgeY][kEdgeX][kTileObs];
+    // the next block along y without being copied.  The MFMA kernel takes
+    // eight slots (slot arithmetic is a mask), the VALU kernel, which holds
+    // more LDS, the five it needs.
+    constexpr int kRingRows = kMfma ? 8 : kEdgeY;
+    static_assert(kEdgeY <= 8 && kPBY < kEdgeY, "a block's edge rows fit the ring");
+    auto ring = [](int x) { return kMfma ? (x & 7) : (x >= kEdgeY ? x - kEdgeY : x); };
+    __shared__ float sS[kRingRows][kEdgeX][kTileObs];
     __shared__ __attribute__((aligned(16))) __bf16 sAhi[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) __bf16 sAlo[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sA32[kTileObs][kPrismsPerStep];
@@ -143,13 +148,17 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     const int64_t tile = blockIdx.x / nchunk;
     const int t = threadIdx.x;
     const int lo_ = t & 63;          // observation within the tile (phases 1-2), lane (phase 3)
-    const int wv = t >> 6;           // wave index 0..3
+    // wave index 0..3, made wave-uniform for the compiler (readfirstlane), so
+    // that the edge rows, prism rows and their bounds checks that depend on it
+    // use scalar loads and branches instead of per-lane masks
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int64_t o = tile * kTileObs + lo_;
     const int64_t oc = o < n ? o : n - 1;
     const double xo = ox[oc], yo = oy[oc], zo = oz[oc];
     const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
     const int64_t b0 = (int64_t)chunk * blocks_per_chunk;
     const int64_t b1 = b0 + blocks_per_chunk < nblk ? b0 + blocks_per_chunk : nblk;
+    const int bi0 = (int)(b0 / nby), bj0 = (int)(b0 - (int64_t)bi0 * nby);
 
     // phase-3 roles
     const int r0 = 32 * (wv & 1), c0 = 32 * (wv >> 1);
@@ -189,12 +198,10 @@ __global__ __launch_bounds__(256) void k_forward_multi(
         int nacc = 0;
         float cxr[kEdgeX];              // x offsets of the current block row's edges
         bool vx[kEdgeX];
+        int bi = bi0, bj = bj0;         // block coordinates of blk, stepped along y
         for (int64_t blk = b0; blk < b1; ++blk) {
-            const int bi = (int)(blk / nby);
-            const int bj = (int)(blk - (int64_t)bi * nby);
             const int i0 = bi * kPBX, j0 = bj * kPBY;
             const bool fresh = blk == b0 || bj == 0;
-            // this step's model operands, loaded while the edge terms compute
             if (fresh) {
                 slot0 = 0;
 #pragma unroll
@@ -204,8 +211,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                     cxr[ii] = column_offset(xn[a <= nx ? a : nx], xo);
                 }
             } else {
-                slot0 += kPBY;
-                if (slot0 >= kEdgeY) slot0 -= kEdgeY;
+                slot0 = ring(slot0 + kPBY);
             }
             // phase 1: edge terms S of edge row q (y node j0 + q) at the x
             // edges ii with (ii mod 4) == wv, or at all of them
@@ -214,8 +220,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                 const int b = j0 + q;
                 const bool vy = b <= ny;
                 const float cy = column_offset(yn[vy ? b : ny], yo);
-                int slot = slot0 + q;
-                if (slot >= kEdgeY) slot -= kEdgeY;
+                const int slot = ring(slot0 + q);
 #pragma unroll
                 for (int ii = 0; ii < kEdgeX; ++ii) {
                     if (all_x || (ii & 3) == wv) {
@@ -248,9 +253,7 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                 float g4[kPBY];
 #pragma unroll
                 for (int q = 0; q < kPBY; ++q) {
-                    int s0 = slot0 + q;
-                    if (s0 >= kEdgeY) s0 -= kEdgeY;
-                    const int s1 = s0 + 1 < kEdgeY ? s0 + 1 : 0;
+                    const int s0 = ring(slot0 + q), s1 = ring(slot0 + q + 1);
                     float G = (sS[s0][ii][lo_] - sS[s0][ii + 1][lo_]) -
                               (sS[s1][ii][lo_] - sS[s1][ii + 1][lo_]);
                     G = (i0 + ii < nx && j0 + q < ny) ? G : 0.0f;
@@ -310,6 +313,10 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             if (++nacc == kFlushBlocks) {
                 flush();
                 nacc = 0;
+            }
+            if (++bj == nby) {
+                bj = 0;
+                ++bi;
             }
         }
         if (nacc > 0) flush();
