@@ -356,10 +356,11 @@ int grav_forward_static(const grav_mesh *mesh, const grav_obs *obs, const double
  * and requests that arrive meanwhile join at the next step.  A request's launch
  * plan depends only on its own shape, so its result is bitwise the same alone
  * and in any mix.  A forward request is bitwise the same as grav_forward
- * (GRAV_MIXED).  An inversion's adjoint splits the observations into fewer
- * parts than grav_invert's does once a problem has more than a few thousand
- * observations (a batched launch fills the GPU with every request's waves),
- * so it agrees with grav_invert to rounding there and bitwise below that.
+ * (GRAV_MIXED).  An inversion's sweeps split the work into fewer observation
+ * parts (adjoint) and column chunks (forward) than grav_invert's do once a
+ * problem is larger than a few thousand observations or a few thousand node
+ * columns (a batched launch fills the GPU with every request's waves), so it
+ * agrees with grav_invert to rounding there and bitwise below that.
  * Requests may be submitted from any thread.
  * ------------------------------------------------------------------------ */
 typedef struct grav_server grav_server;

@@ -88,7 +88,7 @@ struct NodeAdjointPlan {
     int64_t obs_per_part;
 };
 
-ForwardPlan plan_forward(int64_t ncols, int64_t n);
+ForwardPlan plan_forward(int64_t ncols, int64_t n, int64_t target_waves = 0);   // 0 = default
 // target_waves, max_partial_bytes: 0 = the single-call defaults
 AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n, int64_t target_waves = 0,
                          int64_t max_partial_bytes = 0);

@@ -62,6 +62,11 @@ constexpr int kTraceSlot = 7;        // trace(G C G^T) when computed
 // single call to fill the GPU, and its partial sums stay small in the pool.
 constexpr int64_t kServerTargetWavesAdj = 32768;
 constexpr int64_t kServerMaxPartialBytes = int64_t(512) << 20;
+// Forward plan of an inversion's CG iterations, for the same reason: fewer
+// column chunks, so the per-iteration reduction of the chunk partial sums
+// reads less.  A forward request keeps the single-call plan, so that its
+// result is bitwise that of grav_forward.
+constexpr int64_t kServerTargetWavesFwdCG = 16384;
 
 struct FwdJob {
     const double *xn, *yn, *zn, *ox, *oy, *oz, *w2;
@@ -200,7 +205,7 @@ size_t request_layout(Request &q, char *base) {
     ar.size = base ? q.bytes : ~size_t(0) >> 1;
     const Mesh &g = q.g;
     const int64_t n = q.o.n;
-    q.fp = plan_forward(g.ncols(), n);
+    q.fp = plan_forward(g.ncols(), n, q.r.kind == GRAV_REQ_INVERT ? kServerTargetWavesFwdCG : 0);
     q.hk = ar.take<float>(layer_table_len(g.nz));
     q.w2 = ar.take<double>(g.nsegs());
     q.fpart = ar.take<double>((size_t)q.fp.nchunk * n);

@@ -442,11 +442,12 @@ static int64_t round8_capped(int64_t want, int64_t cap) {
     return v;
 }
 
-ForwardPlan plan_forward(int64_t ncols, int64_t n) {
+ForwardPlan plan_forward(int64_t ncols, int64_t n, int64_t target_waves) {
+    if (target_waves <= 0) target_waves = kTargetWavesFwd;
     ForwardPlan p;
     p.nblk_obs = ceil_div(n, kBlock);
     const int64_t waves_obs = ceil_div(n, 64);
-    const int64_t nchunk = round8_capped(ceil_div(kTargetWavesFwd, waves_obs),
+    const int64_t nchunk = round8_capped(ceil_div(target_waves, waves_obs),
                                          ncols / kMinColsPerChunk);
     p.cols_per_chunk = ceil_div(ncols, nchunk);
     p.nchunk = (int)ceil_div(ncols, p.cols_per_chunk);
