@@ -661,6 +661,9 @@ def main() -> int:
         extras["adjoint_pairs_per_s"] = pairs / t_adj
         extras["adjoint_ms"] = 1e3 * t_adj
         extras["adjoint_kernel_ms"] = a_ms / max(a_n, 1)
+        # the adjoint evaluates the same edge segments: the same slot count
+        # per launch against the same peak
+        extras["adjoint_roofline_frac"] = slots / (extras["adjoint_kernel_ms"] * 1e-3) / PEAK_SLOTS
 
         ctx.reset_timing()
         torch.cuda.synchronize()
