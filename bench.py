@@ -493,8 +493,15 @@ def run_issue_probe(args) -> int:
     import paper_2602_03857_amd as g
     with g.Context(0) as ctx:
         r = ctx.issue_rates()
+        pr = ctx.issue_pair_rates()
     fma = r["fma32"]
+    # half FMA, half another class: the rate of the two halves run in sequence
+    serial = {"log": 2.0 / (1.0 / fma + 1.0 / r["log"]),
+              "select": 2.0 / (1.0 / fma + 1.0 / pr["select"])}
+    pairs = {k: {"rate": pr[k], "over_sequential": pr[k] / serial["log" if "log" in k else "select"]}
+             for k in pr if k != "select"}
     out = {"metric": "gfx950 issue rates (chain steps/s summed over lanes)", "rates": r,
+           "select_alone": pr["select"], "pairs": pairs,
            "fma32_per_peak_slot": fma / PEAK_SLOTS,
            "slots_per_instruction": {k: (fma / r[k] - fma / r["add32"] if k in ("log", "rcp", "sqrt")
                                          else fma / r[k]) for k in r},

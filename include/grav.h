@@ -462,6 +462,20 @@ int grav_set_timing(grav_ctx *ctx, int32_t enable);
  * Runs about 20 ms of device work; waits for it.
  * Errors: GRAV_EINVAL (null ctx/rates), GRAV_ENOMEM, GRAV_EDEVICE. */
 int grav_issue_rates(grav_ctx *ctx, double *rates, grav_stream stream);
+
+/* Diagnostics: issue rates of pairs of instruction classes, measured like
+ * grav_issue_rates.  rates (HOST, 5 doubles) receives chain steps per second
+ * summed over lanes; in [0]-[3] half of the chains are FP32 FMA and half of
+ * the other class:
+ *   [0] v_log_f32 + add chains on alternating waves (even waves FMA, odd
+ *       waves the other class), [1] the same two classes interleaved in every
+ *       wave, [2] v_cmp + v_cndmask + add chains on alternating waves,
+ *   [3] interleaved, [4] the compare-and-select chains alone.
+ * With r_a, r_b the single-class rates (grav_issue_rates, or [4]), the two
+ * halves run one after the other would reach 2 / (1/r_a + 1/r_b); a higher
+ * rate is work issued together.
+ * Errors: GRAV_EINVAL (null ctx/rates), GRAV_ENOMEM, GRAV_EDEVICE. */
+int grav_issue_pair_rates(grav_ctx *ctx, double *rates, grav_stream stream);
 int grav_kernel_time(grav_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
 int grav_reset_timing(grav_ctx *ctx);
 

@@ -118,6 +118,7 @@ def _load():
         "grav_server_destroy": (None, [vp]),
         "grav_set_timing": (ctypes.c_int, [vp, i32]),
         "grav_issue_rates": (ctypes.c_int, [vp, P(dbl), vp]),
+        "grav_issue_pair_rates": (ctypes.c_int, [vp, P(dbl), vp]),
         "grav_kernel_time": (ctypes.c_int, [vp, ctypes.c_char_p, P(dbl), P(i64)]),
         "grav_reset_timing": (ctypes.c_int, [vp]),
     }
@@ -135,6 +136,6 @@ EXPORTED = [
     "grav_workspace_bytes", "grav_forward", "grav_adjoint", "grav_dataspace_apply", "grav_trace",
     "grav_trend_surface",
     "grav_invert", "grav_invert_sections", "grav_forward_multi", "grav_forward_static", "grav_set_timing", "grav_kernel_time",
-    "grav_reset_timing", "grav_issue_rates", "grav_server_create", "grav_server_submit", "grav_server_poll",
+    "grav_reset_timing", "grav_issue_rates", "grav_issue_pair_rates", "grav_server_create", "grav_server_submit", "grav_server_poll",
     "grav_server_wait", "grav_server_cancel", "grav_server_destroy",
 ]

@@ -217,6 +217,15 @@ class Context:
         self._rc(lib.grav_issue_rates(self._h, r, self._stream(stream)))
         return dict(zip(("fma32", "log", "rcp", "sqrt", "fma64", "add32"), list(r)))
 
+    def issue_pair_rates(self, stream=None):
+        """Issue rates (chain steps per second summed over lanes) of FP32 FMA
+        chains mixed half and half with transcendental or compare-and-select
+        chains, on alternating waves and interleaved in every wave."""
+        r = (ctypes.c_double * 5)()
+        self._rc(lib.grav_issue_pair_rates(self._h, r, self._stream(stream)))
+        return dict(zip(("fma_log_alternating", "fma_log_interleaved", "fma_select_alternating",
+                         "fma_select_interleaved", "select"), list(r)))
+
     def trend_surface(self, x, y, v, degree=2, resid=None, trend=None, stream=None):
         """Least-squares trend surface of `degree` (1 or 2) through (x, y, v)
         (device float64 vectors of one length).  Returns (coef[6], frame

@@ -371,6 +371,12 @@ extern "C" int grav_issue_rates(grav_ctx *ctx, double *rates, grav_stream stream
     return grav::op_issue_rates(ctx, rates, reinterpret_cast<hipStream_t>(stream));
 }
 
+extern "C" int grav_issue_pair_rates(grav_ctx *ctx, double *rates, grav_stream stream) {
+    ENTER(ctx);
+    if (!rates) return fail(ctx, GRAV_EINVAL, "rates is NULL");
+    return grav::op_issue_pair_rates(ctx, rates, reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" int grav_trend_surface(grav_ctx *ctx, const double *x, const double *y, const double *v,
                                   int64_t n, int32_t degree, double *coef, double *frame,
                                   double *resid, double *trend, grav_stream stream) {

@@ -65,6 +65,7 @@ int op_trend_surface(grav_ctx *ctx, const double *x, const double *y, const doub
                      hipStream_t st);
 uint64_t trend_workspace_need();
 int op_issue_rates(grav_ctx *ctx, double *rates, hipStream_t st);
+int op_issue_pair_rates(grav_ctx *ctx, double *rates, hipStream_t st);
 int op_trace(grav_ctx *ctx, Arena &ar, const Mesh &g, const Obs &o, const double *wdepth,
              double *trace, double *diag, grav_prec prec, hipStream_t st);
 constexpr int kMaxSections = 64;
