@@ -417,8 +417,8 @@ inline unsigned grid_for(int64_t len, int block = 256, int64_t cap = 8192) {
 // 4.6 % more from 57k -> 143k (0.7 % more at 286k, for twice the partial
 // sums).  Chunk and part counts are a multiple of 8 (one residue class per
 // XCD), capped so that every chunk keeps >= 8 node columns and every
-// observation part >= 64 observations and 2 GiB of partial sums (1.07 GB at
-// paper scale).
+// observation part >= 16 observations (64 for the FP64 node adjoint) and
+// 2 GiB of partial sums (1.07 GB at paper scale).
 #ifndef GRAV_TARGET_WAVES_FWD
 #define GRAV_TARGET_WAVES_FWD 131072
 #endif
@@ -428,7 +428,12 @@ inline unsigned grid_for(int64_t len, int block = 256, int64_t cap = 8192) {
 static constexpr int64_t kTargetWavesFwd = GRAV_TARGET_WAVES_FWD;
 static constexpr int64_t kTargetWavesAdj = GRAV_TARGET_WAVES_ADJ;
 static constexpr int64_t kMinColsPerChunk = 8;
-static constexpr int64_t kMinObsPerPart = 64;
+// At least 16 observations per part of the mixed adjoint: small surveys
+// (about a thousand stations) then split into enough parts to fill the GPU
+// (the 32 x 32 x 16 dyke problem's adjoint: 0.25 -> 0.10 ms).  The FP64
+// node adjoint keeps 64 (it is the comparator path).
+static constexpr int64_t kMinObsPerPart = 16;
+static constexpr int64_t kMinObsPerPartNodes = 64;
 #ifndef GRAV_MAX_PARTIAL_MIB
 #define GRAV_MAX_PARTIAL_MIB 2048
 #endif
@@ -485,7 +490,7 @@ NodeAdjointPlan plan_adjoint_nodes(int64_t nnodes, int64_t n) {
     NodeAdjointPlan p;
     p.nblk_node = ceil_div(nnodes, kBlock);
     const int64_t waves = p.nblk_node * (kBlock / 64);
-    int64_t cap = n / kMinObsPerPart;
+    int64_t cap = n / kMinObsPerPartNodes;
     const int64_t mem_cap = kMaxPartialBytes / (nnodes * 8);
     if (mem_cap < cap) cap = mem_cap;
     const int64_t parts = round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
@@ -522,7 +527,7 @@ int64_t adjoint_parts_bound(int64_t ncols, int nz, int64_t n) {
 
 int64_t node_adjoint_parts_bound(int64_t nnodes, int64_t n) {
     const int64_t waves = ceil_div(nnodes, kBlock) * (kBlock / 64);
-    int64_t cap = n / kMinObsPerPart;
+    int64_t cap = n / kMinObsPerPartNodes;
     const int64_t mem_cap = kMaxPartialBytes / (nnodes * 8);
     if (mem_cap < cap) cap = mem_cap;
     return round8_capped(ceil_div(kTargetWavesAdj, waves), cap);
