@@ -487,6 +487,40 @@ def run_profile_op(args) -> int:
     return 0
 
 
+def run_cg_graph(args) -> int:
+    """Small CG solves with the kernels launched one by one against the same
+    iterations replayed from a HIP graph (grav_cg_opts.graph)."""
+    import torch
+    import paper_2602_03857_amd as g
+    from oracle import prism
+    dev = torch.device("cuda", 0)
+    res = {}
+    for p in (workloads.dykes_32x32x16(), workloads.random_case(7, 60, 50, 40, 5000)):
+        mesh = g.DeviceMesh.from_mesh(p.mesh, dev)
+        obs = g.DeviceObs.from_survey(p.obs, dev)
+        d = torch.as_tensor(prism.forward(p.mesh, p.obs, p.m), device=dev)
+        w = torch.as_tensor(p.wdepth, device=dev)
+        row = {"n_obs": p.obs.n, "n_cells": p.mesh.ncells}
+        with g.Context(0, validate=False) as ctx:
+            for graph in (False, True):
+                ctx.invert(mesh, obs, d, w, lam=-1.0, tol=1e-6, max_iter=300, graph=graph)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    _, _, info = ctx.invert(mesh, obs, d, w, lam=-1.0, tol=1e-6, max_iter=300,
+                                            graph=graph)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / args.steps
+                key = "graph" if graph else "eager"
+                row[key + "_ms_per_solve"] = ms
+                row[key + "_iterations"] = info["iters"]
+        row["speedup"] = row["eager_ms_per_solve"] / row["graph_ms_per_solve"]
+        res[p.name] = row
+    print(json.dumps({"metric": "CG solve time, kernels one by one vs graph replay", "solves": res}),
+          flush=True)
+    return 0
+
+
 def run_issue_probe(args) -> int:
     """Measure the issue rates behind the roofline's slot weights."""
     import torch  # noqa: F401
@@ -524,6 +558,8 @@ def main() -> int:
     ap.add_argument("--serve", action="store_true", help="replay the serving stream instead")
     ap.add_argument("--cg-full", action="store_true",
                     help="time the paper-scale 50-iteration CG solve instead")
+    ap.add_argument("--cg-graph", action="store_true",
+                    help="small CG solves: kernels one by one vs iterations replayed from a HIP graph")
     ap.add_argument("--cg-compare", action="store_true",
                     help="paper-scale CG: mixed vs FP64 histories, plain vs Jacobi")
     ap.add_argument("--cg-compare-iters", type=int, default=6)
@@ -558,6 +594,8 @@ def main() -> int:
         return run_cg_compare(args)
     if args.issue_probe:
         return run_issue_probe(args)
+    if args.cg_graph:
+        return run_cg_graph(args)
     if args.profile_op:
         return run_profile_op(args)
     if args.copy_probe:

@@ -210,6 +210,13 @@ typedef struct {
      * y0.  grav_invert only: the server requires both NULL. */
     const double *y0;
     double *y_out;
+    /* 1: each plain or Jacobi CG iteration (the operator, dot products and
+     * vector updates, up to the convergence check) is captured once per solve
+     * into a HIP graph and replayed on `stream`: the same kernels with the
+     * same arguments, fewer launches.  Ignored with restart > 0 or with kernel
+     * timing on.  0: the kernels are launched one by one.  The server ignores
+     * it. */
+    int32_t graph;
 } grav_cg_opts;
 
 typedef struct {

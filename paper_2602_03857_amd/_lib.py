@@ -37,7 +37,7 @@ class CgOpts(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("max_halvings", ctypes.c_int32), ("history_cap", ctypes.c_int32),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("y0", ctypes.c_void_p),
-                ("y_out", ctypes.c_void_p)]
+                ("y_out", ctypes.c_void_p), ("graph", ctypes.c_int32)]
 
 
 class CgInfo(ctypes.Structure):

@@ -248,7 +248,7 @@ class Context:
     def invert(self, mesh, obs, d_obs, wdepth, lam=-1.0, m_ref=None, tol=1e-6, max_iter=200,
                fixed_iters=0, m_out=None, d_pred=None, want_pred=False, prec=GRAV_MIXED,
                stream=None, precond=0, restart=0, max_cycles=30, max_halvings=5,
-               history_cap=0, y0=None, y_out=None):
+               history_cap=0, y0=None, y_out=None, graph=False):
         """Data-space CG inversion (Eq. 11).  Returns (m, d_pred or None, info dict).
 
         restart > 0 selects the restarted policy (cycles of at most `restart`
@@ -257,7 +257,8 @@ class Context:
         history_cap > 0 returns the misfit log (relative residual after each
         CG iteration, at most history_cap entries) as info["history"].
         y0 (n,) starts CG from that data-space iterate (warm start / resume);
-        y_out (n,) receives the final iterate."""
+        y_out (n,) receives the final iterate.  graph=True replays each plain
+        or Jacobi CG iteration from a HIP graph captured once per solve."""
         _check(d_obs, torch.float64, obs.n, "d_obs", self.device)
         _check(wdepth, torch.float64, mesh.ncells, "wdepth", self.device)
         if m_ref is not None:
@@ -277,7 +278,7 @@ class Context:
                     int(max_cycles), int(max_halvings), int(history_cap),
                     ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if history_cap > 0 else None,
                     y0.data_ptr() if y0 is not None else None,
-                    y_out.data_ptr() if y_out is not None else None)
+                    y_out.data_ptr() if y_out is not None else None, int(bool(graph)))
         info = CgInfo()
         rc = lib.grav_invert(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c), d_obs.data_ptr(),
                              wdepth.data_ptr(), float(lam),
@@ -296,7 +297,7 @@ class Context:
                         data_scope="section", model_degree=2, lam=-1.0, tol=1e-6, max_iter=200,
                         fixed_iters=0, precond=0, restart=0, max_cycles=30, max_halvings=5,
                         m_out=None, m_detrended=None, detrend=True, prec=GRAV_MIXED,
-                        stream=None):
+                        stream=None, graph=False):
         """Regional inversion by adjoining sections along y (split at the mesh
         node rows `ysplit`, 0 ... ny), each inverted on its own, combined, and
         (detrend) a per-layer trend surface of `model_degree` removed.
@@ -317,7 +318,7 @@ class Context:
         so = SectionOpts(nsec, ctypes.cast(split, ctypes.POINTER(ctypes.c_int32)), int(data_degree),
                          scope, int(model_degree))
         cg = CgOpts(float(tol), int(max_iter), int(fixed_iters), int(precond), int(restart),
-                    int(max_cycles), int(max_halvings), 0, None, None, None)
+                    int(max_cycles), int(max_halvings), 0, None, None, None, int(bool(graph)))
         infos = (CgInfo * max(nsec, 1))()
         rc = lib.grav_invert_sections(self._h, ctypes.byref(mesh.c), ctypes.byref(obs.c),
                                       d_obs.data_ptr(), wdepth.data_ptr(), float(lam),

@@ -265,6 +265,7 @@ extern "C" void grav_ctx_destroy(grav_ctx *ctx) {
     (void)grav_reset_timing(ctx);
     (void)hipFree(ctx->ws);
     (void)hipHostFree(ctx->h_pinned);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -465,6 +466,7 @@ int check_cg_opts(grav_ctx *ctx, const grav_cg_opts *cg) {
     }
     if (cg->precond != 0 && cg->precond != 1)
         return fail(ctx, GRAV_EINVAL, "precond must be 0 (none) or 1 (Jacobi)");
+    if (cg->graph != 0 && cg->graph != 1) return fail(ctx, GRAV_EINVAL, "graph must be 0 or 1");
     return GRAV_OK;
 }
 

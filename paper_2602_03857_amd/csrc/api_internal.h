@@ -22,6 +22,7 @@ struct grav_ctx {
     std::string err;
     size_t arena_skip = 0;  // bytes at the arena's head held by an enclosing workflow
     bool timing = false;    // record events around sweep launches
+    hipStream_t cap_stream = nullptr;   // for capturing CG iterations into a graph (lazily created)
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::map<std::string, std::pair<double, int64_t>> totals;
 };

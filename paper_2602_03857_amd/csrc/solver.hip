@@ -26,6 +26,19 @@ struct RoctxRange {
         if (_e != hipSuccess) return hip_fail(ctx, _e, where);     \
     } while (0)
 
+// A HIP graph and its executable, destroyed with the object.
+struct IterGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    IterGraph() = default;
+    IterGraph(const IterGraph &) = delete;
+    IterGraph &operator=(const IterGraph &) = delete;
+    ~IterGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 static int read_scalars(grav_ctx *ctx, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(ctx->h_scal, ctx_scalars(ctx), kNumScalars * sizeof(double),
                            hipMemcpyDeviceToHost, st), "scalar copy");
@@ -201,20 +214,48 @@ int run_invert(grav_ctx *ctx, const Mesh &g, const Obs &o, const double *d_obs,
         relres = ss.relres;
         converged = ss.converged;
     }
+    // One iteration up to its convergence check: q = A p, alpha, y, r (z) and
+    // the new residual norm, all on the device.
+    auto iteration = [&](hipStream_t s) -> int {
+        int irc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, s);
+        if (irc) return irc;
+        HIP_TRY(launch_dot(p, q, n, dpart, s), "dot");
+        if (pc) {
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQPrecond, 0, s), "dot");
+            HIP_TRY(launch_pcg_update_yrz(y, r, z, p, q, dinv, n, scal, dpart, dpart2, s), "pcg update");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kRR, s), "dot");
+            HIP_TRY(launch_dot_finish(dpart2, scal, kFinishRZNew, 0, s), "dot");
+        } else {
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQ, 0, s), "dot");
+            HIP_TRY(launch_cg_update_yr(y, r, p, q, n, scal, dpart, s), "cg update");
+            HIP_TRY(launch_dot_finish(dpart, scal, kFinishRRNew, 0, s), "dot");
+        }
+        return GRAV_OK;
+    };
+    // cg.graph: the iteration's launches are captured once, on a stream of the
+    // context (the caller's stream may be the null stream, which cannot be
+    // captured), and replayed on the caller's stream; they take the same
+    // pointers every iteration.  Not with kernel timing on (its events would
+    // be captured too).
+    IterGraph ig;
+    const bool graph = cg.graph != 0 && !restarted && !ctx->timing && it < iters_cap && !converged;
+    if (graph) {
+        if (!ctx->cap_stream)
+            HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream");
+        HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        const int crc = iteration(ctx->cap_stream);
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &ig.graph);
+        if (crc) return crc;
+        HIP_TRY(ce, "end capture");
+        HIP_TRY(hipGraphInstantiate(&ig.exec, ig.graph, nullptr, nullptr, 0), "graph instantiate");
+    }
     for (it = restarted ? it : 0; it < iters_cap && !converged;) {
         const RoctxRange range("grav cg iteration");
-        rc = op_dataspace(ctx, ar, g, o, wdepth, lambda, p, q, prec, st);
-        if (rc) return rc;
-        HIP_TRY(launch_dot(p, q, n, dpart, st), "dot");
-        if (pc) {
-            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQPrecond, 0, st), "dot");
-            HIP_TRY(launch_pcg_update_yrz(y, r, z, p, q, dinv, n, scal, dpart, dpart2, st), "pcg update");
-            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPlain, kRR, st), "dot");
-            HIP_TRY(launch_dot_finish(dpart2, scal, kFinishRZNew, 0, st), "dot");
+        if (graph) {
+            HIP_TRY(hipGraphLaunch(ig.exec, st), "graph launch");
         } else {
-            HIP_TRY(launch_dot_finish(dpart, scal, kFinishPQ, 0, st), "dot");
-            HIP_TRY(launch_cg_update_yr(y, r, p, q, n, scal, dpart, st), "cg update");
-            HIP_TRY(launch_dot_finish(dpart, scal, kFinishRRNew, 0, st), "dot");
+            rc = iteration(st);
+            if (rc) return rc;
         }
         ++it;
         if (!fixed) {
