@@ -33,28 +33,60 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 
-# Roofline of the forward sweep (an instruction-issue-bound kernel).
+# Roofline of the sweeps (instruction-issue-bound kernels).
 # Peak: MI355X FP32 vector 157.3 TFLOP/s = 78.65e12 full-rate lane operations
 # per second (FMA = one operation).  Algorithmic cost of one (observation,
 # vertical edge segment) pair: the minimal gfx950 instruction sequence of the
 # edge-segment formula (per-operation table in the design notes), 94
-# instructions for layers near the top and 72 for "deep" layers (top at least
-# 9 thicknesses and 1 mm below the mesh top, where the atan difference needs no
-# range reduction, no limit select is needed and the log1p arguments stay
-# below 1/4).  6 of them are transcendental (1 sqrt, 3 rcp, 2 log) and 2 are
-# FP64.  Issue cost relative to an FP32 add, measured with --issue-probe
-# (dependent chains of one instruction class): a transcendental takes 2 slots,
-# an FP64 FMA 1; issue slots per pair = instructions + 6 * (2 - 1).
+# instructions (6 transcendental: 1 sqrt, 3 rcp, 2 log) for layers near the
+# top, and for "deep" layers (top at least 9 thicknesses and 1 mm below the
+# mesh top, where the atan difference needs no range reduction, no limit
+# select is needed and the log1p arguments stay below 1/4) 58 in the forward
+# and 56 in the adjoint (5 transcendental): there atan(u2) is carried down the
+# column by the atan addition formula, one FP64 add with two conversions in
+# the forward and one FP32 add in the adjoint's walks of at most 16 layers,
+# instead of a range-reduced atan.  Every walk down deep layers starts its
+# angle with one range-reduced atan (17 instructions, 1 transcendental): once
+# per (observation, column) in the forward and once per (observation, column,
+# deep layer chunk) in the adjoint.  Issue cost relative to an FP32 add,
+# measured with --issue-probe (dependent chains of one instruction class): a
+# transcendental takes 2 slots, an FP64 instruction 1; issue slots =
+# instructions + transcendentals * (2 - 1).
 PEAK_SLOTS = 157.3e12 / 2.0
-INSTR_SHALLOW, INSTR_DEEP = 94, 72
-N_TRANS, N_FP64 = 6, 2
+INSTR_SHALLOW, TRANS_SHALLOW = 94, 6
+INSTR_DEEP_FWD, INSTR_DEEP_ADJ, TRANS_DEEP = 58, 56, 5
+INSTR_ANCHOR, TRANS_ANCHOR = 17, 1
 TRANS_COST, FP64_COST = 2, 1
+ADJ_LAYERS = 16          # layers per lane in the mixed adjoint (chunk plan below)
 DEEP_RATIO = 9.0
 DEEP_MIN_DEPTH = 1e-3
 
 
-def slots_per_pair(instr: int) -> int:
-    return instr + N_TRANS * (TRANS_COST - 1) + N_FP64 * (FP64_COST - 1)
+def slots(instr: int, trans: int) -> int:
+    return instr + trans * (TRANS_COST - 1)
+
+
+def adjoint_deep_chunks(nz: int, kdeep: int) -> int:
+    """Layer chunks of the mixed adjoint that start at or below the first deep
+    layer (the library's plan: ceil(nz / 16) chunks, the first nz mod chunks
+    one layer longer)."""
+    nkc = -(-nz // ADJ_LAYERS)
+    kq, kr = divmod(nz, nkc)
+    return sum(1 for kc in range(nkc) if kc * kq + min(kc, kr) >= kdeep)
+
+
+def sweep_costs(n: int, ncols: int, nz: int, kdeep: int):
+    """(instructions, issue slots) per launch of the forward and of the adjoint."""
+    ndeep = nz - kdeep
+    fwd_i = kdeep * INSTR_SHALLOW + ndeep * INSTR_DEEP_FWD + (INSTR_ANCHOR if ndeep else 0)
+    fwd_s = (kdeep * slots(INSTR_SHALLOW, TRANS_SHALLOW) + ndeep * slots(INSTR_DEEP_FWD, TRANS_DEEP)
+             + (slots(INSTR_ANCHOR, TRANS_ANCHOR) if ndeep else 0))
+    nch = adjoint_deep_chunks(nz, kdeep)
+    adj_i = kdeep * INSTR_SHALLOW + ndeep * INSTR_DEEP_ADJ + nch * INSTR_ANCHOR
+    adj_s = (kdeep * slots(INSTR_SHALLOW, TRANS_SHALLOW) + ndeep * slots(INSTR_DEEP_ADJ, TRANS_DEEP)
+             + nch * slots(INSTR_ANCHOR, TRANS_ANCHOR))
+    k = n * ncols
+    return {"fwd": (k * fwd_i, k * fwd_s), "adj": (k * adj_i, k * adj_s)}
 
 
 def first_deep_layer(zn) -> int:
@@ -667,9 +699,8 @@ def main() -> int:
     kdeep = first_deep_layer(p.mesh.zn)
     nz = p.mesh.nz
     segs = ncols * nz
-    instr = n * ncols * (kdeep * INSTR_SHALLOW + (nz - kdeep) * INSTR_DEEP)
-    slots = n * ncols * (kdeep * slots_per_pair(INSTR_SHALLOW)
-                         + (nz - kdeep) * slots_per_pair(INSTR_DEEP))
+    costs = sweep_costs(n, ncols, nz, kdeep)
+    instr, slots_fwd = costs["fwd"]
     k_s = k_avg_ms * 1e-3
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -677,10 +708,10 @@ def main() -> int:
             tr = json.load(fh)
         if tr.get("source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": slots / k_s / 1e12, "peak": PEAK_SLOTS / 1e12,
-                "unit": "T lane-slots/s", "frac": slots / k_s / PEAK_SLOTS, "traffic": traffic,
+    roofline = {"bound": "alu", "achieved": slots_fwd / k_s / 1e12, "peak": PEAK_SLOTS / 1e12,
+                "unit": "T lane-slots/s", "frac": slots_fwd / k_s / PEAK_SLOTS, "traffic": traffic,
                 "kernel": "k_forward_mixed", "kernel_ms": k_avg_ms,
-                "segments_per_launch": segs * n, "slots_per_launch": slots,
+                "segments_per_launch": segs * n, "slots_per_launch": slots_fwd,
                 "frac_unweighted_instructions": instr / k_s / PEAK_SLOTS}
 
     # error vs the oracle on the stored rows
@@ -706,9 +737,10 @@ def main() -> int:
         extras["adjoint_pairs_per_s"] = pairs / t_adj
         extras["adjoint_ms"] = 1e3 * t_adj
         extras["adjoint_kernel_ms"] = a_ms / max(a_n, 1)
-        # the adjoint evaluates the same edge segments: the same slot count
-        # per launch against the same peak
-        extras["adjoint_roofline_frac"] = slots / (extras["adjoint_kernel_ms"] * 1e-3) / PEAK_SLOTS
+        # the same edge segments at the adjoint's own instruction counts,
+        # against the same peak
+        extras["adjoint_roofline_frac"] = (costs["adj"][1] / (extras["adjoint_kernel_ms"] * 1e-3)
+                                           / PEAK_SLOTS)
 
         ctx.reset_timing()
         torch.cuda.synchronize()

@@ -18,7 +18,10 @@
 //      (u2 - u1) / (1 + u1 u2)     = -xy h (z1 + z2)(x^2 + y^2 + z1^2 + z2^2)
 //                                     / ((z1 R1 + z2 R2)(z1 z2 R1 R2 + x^2 y^2))
 //    with u = xy / (z R).  The last identity needs 1 + u1 u2 > 0, which holds
-//    because z1, z2 >= 0 (observations on or above the mesh top).
+//    because z1, z2 >= 0 (observations on or above the mesh top).  By the same
+//    addition formula atan(u2) = atan(u1) + atan(delta) with the delta above,
+//    so in layers where atan(delta) is cheap (deep layers, below) the angle of
+//    the bottom node is carried down the column instead of being evaluated.
 //
 // Singular limits, taken by select (never by multiplying by zero, so that an
 // infinite or NaN intermediate of a discarded branch cannot leak):
@@ -194,10 +197,9 @@ __device__ __forceinline__ Node make_node(const Column &c, float z) {
 // y < 0, dR (R1 + |y|) / (x^2 + z1^2) = dR / (R1 - |y|) <= (z2^2 - z1^2) / z1^2
 // = 2 h / z1 + (h / z1)^2 (using R1 - |y| >= z1^2 / (2 R1) and R2 >= R1), at
 // most 2/9 + 1/81 when z1 >= 9 h; likewise for x.
-template <bool kDeep = false>
-__device__ __forceinline__ float edge_segment(const Column &c, const Node &t, const Node &b,
-                                              float h) {
-    const float hz = h * (t.z + b.z);
+template <bool kDeep>
+__device__ __forceinline__ void edge_logs(const Column &c, const Node &t, const Node &b, float hz,
+                                          float &lnY, float &lnX) {
     // 1/(R1 + y) = (y >= 0) ? 1/(R1 + |y|) : (R1 + |y|)/(x^2 + z1^2) (rationalised
     // for y < 0), likewise for x; a denominator belonging to a discarded log
     // term (x = 0, resp. y = 0) is replaced by 1.
@@ -212,13 +214,23 @@ __device__ __forceinline__ float edge_segment(const Column &c, const Node &t, co
     const float numX = c.xneg ? rx : 1.0f;
     // dR/(R1 + y) and dR/(R1 + x) with dR = hz / (R1 + R2), one reciprocal
     const float q = hz * fm::rcp((t.R + b.R) * (denY * denX));
-    const float lnY = fm::log1p_pos<kDeep>(q * numY * denX);   // ln(R2 + y) - ln(R1 + y)
-    const float lnX = fm::log1p_pos<kDeep>(q * numX * denY);   // ln(R2 + x) - ln(R1 + x)
-    // z2 atan(u2) - z1 atan(u1) = h atan(u2) + z1 atan(delta)
-    const float at2 = fm::atan_ratio(c.xy, b.zR);
+    lnY = fm::log1p_pos<kDeep>(q * numY * denX);   // ln(R2 + y) - ln(R1 + y)
+    lnX = fm::log1p_pos<kDeep>(q * numX * denY);   // ln(R2 + x) - ln(R1 + x)
+}
+
+// atan(delta), delta = (u2 - u1) / (1 + u1 u2).
+template <bool kDeep>
+__device__ __forceinline__ float edge_atan_delta(const Column &c, const Node &t, const Node &b,
+                                                 float hz) {
     const float num = -c.xy * hz * (c.s + t.zz + b.zz);
     const float den = (t.zR + b.zR) * fmaf(t.zR, b.zR, c.xy2);
-    const float atd = kDeep ? fm::atan_small(num * fm::rcp(den)) : fm::atan_ratio(num, den);
+    return kDeep ? fm::atan_small(num * fm::rcp(den)) : fm::atan_ratio(num, den);
+}
+
+// S = h atan(u2) + z1 atan(delta) - x ln(..) - y ln(..)
+template <bool kDeep>
+__device__ __forceinline__ float edge_assemble(const Column &c, const Node &t, float h, float at2,
+                                               float atd, float lnY, float lnX) {
     float S = h * at2;
     if constexpr (kDeep) {
         // z1 > 0 keeps every denominator above zero, so every term is finite
@@ -232,6 +244,56 @@ __device__ __forceinline__ float edge_segment(const Column &c, const Node &t, co
         S = c.ynz ? fmaf(-c.y, lnX, S) : S;
     }
     return S;
+}
+
+// S = Psi(x, y, z2) - Psi(x, y, z1) for one vertical edge segment between
+// node t (top, depth z1 >= 0) and node b (bottom, z2 = z1 + h).
+//
+// kDeep: the segment's layer starts at least 9 h (and at least 1 mm) below the
+// mesh top.  Then z1 > 0, so x^2 + z1^2, y^2 + z1^2, R1 + |y|, R1 + |x| and
+// the atan-difference denominator are all positive for every observation and
+// the limit selects of the general path are not needed.  Since
+// z1 >= (layer top - mesh top) for every observation on or above the top, and
+// the atan-difference argument obeys |delta| <= h (z1 + h) / z1^2 (bound from
+// z1 R1 + z2 R2 >= (z1 + z2) R1, x^2 + y^2 + z1^2 + z2^2 <= 2 R2^2, AM-GM on the
+// denominator and R2/R1 <= z2/z1), such layers have |delta| <= 10/81 < 1/8 for
+// all observations and take atan_small without range reduction.  The log1p
+// arguments there stay below 1/4 as well: dR / (R1 + |y|) <= h / z1, and for
+// y < 0, dR (R1 + |y|) / (x^2 + z1^2) = dR / (R1 - |y|) <= (z2^2 - z1^2) / z1^2
+// = 2 h / z1 + (h / z1)^2 (using R1 - |y| >= z1^2 / (2 R1) and R2 >= R1), at
+// most 2/9 + 1/81 when z1 >= 9 h; likewise for x.
+template <bool kDeep = false>
+__device__ __forceinline__ float edge_segment(const Column &c, const Node &t, const Node &b,
+                                              float h) {
+    const float hz = h * (t.z + b.z);
+    float lnY, lnX;
+    edge_logs<kDeep>(c, t, b, hz, lnY, lnX);
+    // z2 atan(u2) - z1 atan(u1) = h atan(u2) + z1 atan(delta)
+    const float at2 = fm::atan_ratio(c.xy, b.zR);
+    const float atd = edge_atan_delta<kDeep>(c, t, b, hz);
+    return edge_assemble<kDeep>(c, t, h, at2, atd, lnY, lnX);
+}
+
+// Deep-layer segment with atan(u) carried down the column: on entry A holds
+// atan(u1) of the top node, on exit atan(u2) = atan(u1) + atan(delta), the
+// addition formula of atan, exact here because u1 u2 = x^2 y^2 / (z1 R1 z2 R2)
+// >= 0 keeps both angles on one branch.  This replaces the range-reduced
+// atan of the bottom node by one addition; the angle is started once per
+// walk with atan_ratio(xy, zR) at its first node.  Since u is monotone in z
+// along a column, every delta of a walk has the same sign, so the errors of
+// the atan(delta) terms add up to at most their relative error times
+// |A_end - A_start| <= pi/2.  T = double accumulates the angle exactly for
+// walks of any length; T = float adds one rounding of 2^-24 |A| per layer
+// and is for walks of at most 16 layers.
+template <typename T>
+__device__ __forceinline__ float edge_segment_carry(const Column &c, const Node &t, const Node &b,
+                                                    float h, T &A) {
+    const float hz = h * (t.z + b.z);
+    float lnY, lnX;
+    edge_logs<true>(c, t, b, hz, lnY, lnX);
+    const float atd = edge_atan_delta<true>(c, t, b, hz);
+    A += static_cast<T>(atd);
+    return edge_assemble<true>(c, t, h, static_cast<float>(A), atd, lnY, lnX);
 }
 
 // Psi(x, y, z) of Eq. 2 in FP64 (R from Eq. 3); ln(R + y) for y < 0 is taken

@@ -72,6 +72,8 @@ __device__ __forceinline__ void forward_mixed_block(
             acc = fma(static_cast<double>(S), wc, acc);
             top = bot;
         }
+        // atan(u) of the first deep node, carried down the deep layers in FP64
+        double A = k < nz ? static_cast<double>(fm::atan_ratio(c.xy, top.zR)) : 0.0;
 #pragma unroll 16
         for (; k < nz; ++k) {
             const int kn = k + 2 < nz ? k + 2 : nz - 1;
@@ -80,7 +82,7 @@ __device__ __forceinline__ void forward_mixed_block(
             w_a = w_b; h_a = h_b; z_a = z_b;
             w_b = w[kn]; h_b = hk[kn]; z_b = zrel[kn];
             const Node bot = make_node(c, zc + ztop);
-            const float S = edge_segment<true>(c, top, bot, hc);
+            const float S = edge_segment_carry(c, top, bot, hc, A);
             acc = fma(static_cast<double>(S), wc, acc);
             top = bot;
         }
@@ -106,6 +108,8 @@ __device__ __forceinline__ void adjoint_obs(double X, double Y, const float *__r
     const Column c = make_column(X, Y, xo, yo);
     const float ztop = static_cast<float>(zn0 - zo);
     Node top = make_node(c, node_depth(zrel, k0, ztop));
+    // deep chunks carry atan(u) down their (at most 16) layers in FP32
+    float A = kDeep ? fm::atan_ratio(c.xy, top.zR) : 0.0f;
     const int kl = k0 + cnt - 1;
     float za = zrel[k0], zb = zrel[k0 + 1 <= kl ? k0 + 1 : kl];
     float ha = hk[k0], hb = hk[k0 + 1 <= kl ? k0 + 1 : kl];
@@ -117,11 +121,13 @@ __device__ __forceinline__ void adjoint_obs(double X, double Y, const float *__r
             const int n2 = k0 + j + 3 <= kl ? k0 + j + 3 : kl;
             za = zrel[n1]; zb = zrel[n2]; ha = hk[n1]; hb = hk[n2];
             const Node b1 = make_node(c, z1 + ztop);
-            const float S1 = edge_segment<kDeep>(c, top, b1, h1);
+            const float S1 = kDeep ? edge_segment_carry(c, top, b1, h1, A)
+                                   : edge_segment<false>(c, top, b1, h1);
             acc[j] = fma(vo, static_cast<double>(S1), acc[j]);
             if (j + 1 < cnt) {
                 const Node b2 = make_node(c, z2 + ztop);
-                const float S2 = edge_segment<kDeep>(c, b1, b2, h2);
+                const float S2 = kDeep ? edge_segment_carry(c, b1, b2, h2, A)
+                                       : edge_segment<false>(c, b1, b2, h2);
                 acc[j + 1] = fma(vo, static_cast<double>(S2), acc[j + 1]);
                 top = b2;
             }
@@ -159,11 +165,10 @@ __device__ __forceinline__ void adjoint_obs_range(
 }
 
 // Adjoint sweep, one block: lanes own node columns colblk*kBlock + lane and
-// layer chunk kc of nkc (nkc = ceil(nz / kAdjLayers) chunks: the first
-// nz mod nkc hold one layer more than the others), observations of part
-// `part`; writes upart[part][segment] = sum_{o in part} v_o S (FP64, one
-// register pair per layer, no cross-lane reduction).  `lane` as in the forward
-// block.
+// layer chunk kc of nkc (at most 16 consecutive layers, all above the first
+// deep layer or all at or below it), observations of part `part`; writes
+// upart[part][segment] = sum_{o in part} v_o S (FP64, one register pair per
+// layer, no cross-lane reduction).  `lane` as in the forward block.
 __device__ __forceinline__ void adjoint_mixed_block(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int ny1, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
@@ -181,10 +186,21 @@ __device__ __forceinline__ void adjoint_mixed_block(
         a = (int)(colc / ny1);
         b = (int)(colc - (int64_t)a * ny1);
     }
+    // Layer chunks: the layers above the first deep one (kdeep) and the deep
+    // layers are chunked separately, ceil(len / kAdjLayers) balanced chunks each,
+    // so that every deep layer takes the short formula; nkc (from plan_adjoint)
+    // leaves room for both and chunks past them are empty.
+    const int kdeep = reinterpret_cast<const int *>(hk + nz)[0];
+    const int ng = (kdeep + kAdjLayers - 1) / kAdjLayers;
+    const bool deep = kc >= ng;   // uniform per block
+    const int lo = deep ? kdeep : 0, len = deep ? nz - kdeep : kdeep;
+    const int idx = deep ? kc - ng : kc;
+    const int nch = (len + kAdjLayers - 1) / kAdjLayers;
+    if (idx >= nch) return;
+    const int kq = len / nch, kr = len - kq * nch;
+    const int k0 = lo + idx * kq + (idx < kr ? idx : kr);
+    const int cnt = kq + (idx < kr ? 1 : 0);
     const double X = xn[a], Y = yn[b];
-    const int kq = nz / nkc, kr = nz - kq * nkc;
-    const int k0 = kc * kq + (kc < kr ? kc : kr);
-    const int cnt = kq + (kc < kr ? 1 : 0);
     const float *__restrict__ zrel = hk + nz + 1;
     const double zn0 = zn[0];
     double acc[kAdjLayers];
@@ -192,7 +208,6 @@ __device__ __forceinline__ void adjoint_mixed_block(
     for (int j = 0; j < kAdjLayers; ++j) acc[j] = 0.0;
     const int64_t o0 = (int64_t)part * obs_per_part;
     const int64_t o1 = o0 + obs_per_part < n ? o0 + obs_per_part : n;
-    const bool deep = k0 >= reinterpret_cast<const int *>(hk + nz)[0];   // uniform per block
     if (deep)
         adjoint_obs_range<true>(X, Y, zrel, hk, zn0, k0, cnt, ox, oy, oz, v, o0, o1, acc);
     else

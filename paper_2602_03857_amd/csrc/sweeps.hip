@@ -469,13 +469,19 @@ ForwardPlan plan_trace(int nx, int64_t n) {
     return p;
 }
 
+// Layer chunks of the mixed adjoint: the layers above the first deep layer and
+// the deep ones are chunked separately (the split depends on the mesh, known
+// on the device only), ceil(a / 16) + ceil(b / 16) <= ceil(nz / 16) + 1 chunks
+// for a + b = nz; chunk indices past the two ranges are empty.
+static int adjoint_layer_chunks(int nz) { return (int)ceil_div(nz, kAdjLayers) + 1; }
+
 AdjointPlan plan_adjoint(int64_t ncols, int nz, int64_t n, int64_t target_waves,
                          int64_t max_partial_bytes) {
     if (target_waves <= 0) target_waves = kTargetWavesAdj;
     if (max_partial_bytes <= 0) max_partial_bytes = kMaxPartialBytes;
     AdjointPlan p;
     p.nblk_col = ceil_div(ncols, kBlock);
-    p.nkc = (int)ceil_div(nz, kAdjLayers);
+    p.nkc = adjoint_layer_chunks(nz);
     const int64_t waves = p.nblk_col * p.nkc * (kBlock / 64);
     int64_t cap = n / kMinObsPerPart;
     const int64_t mem_cap = max_partial_bytes / (ncols * nz * 8);
@@ -518,7 +524,7 @@ int64_t trace_partials_bound(int nx, int64_t n) {
 }
 
 int64_t adjoint_parts_bound(int64_t ncols, int nz, int64_t n) {
-    const int64_t waves = ceil_div(ncols, kBlock) * ceil_div(nz, kAdjLayers) * (kBlock / 64);
+    const int64_t waves = ceil_div(ncols, kBlock) * adjoint_layer_chunks(nz) * (kBlock / 64);
     int64_t cap = n / kMinObsPerPart;
     const int64_t mem_cap = kMaxPartialBytes / (ncols * nz * 8);
     if (mem_cap < cap) cap = mem_cap;

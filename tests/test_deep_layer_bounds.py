@@ -97,3 +97,71 @@ def test_log1p_without_the_inverse_factor():
     cw = np.float64(np.float32(tw - (uw - np.float32(1.0))))
     rw = abs(np.log(np.float64(uw)) + cw - np.log1p(np.float64(tw))) / np.log1p(np.float64(tw))
     assert 1.4 * 2.0 ** -24 < rw < 2.0 ** -23
+
+
+def _column_walk(rng, n, layers):
+    """n columns, each walked down `layers` deep layers: offsets (x, y) and node
+    depths z_0 < ... < z_layers with z_0 >= 9 h_0 and thicknesses growing
+    downwards, as in the benchmark meshes."""
+    h0 = rng.uniform(1.0, 300.0, n)
+    z0 = h0 * (DEEP_RATIO + rng.exponential(3.0, n) * (rng.random(n) < 0.7))
+    grow = rng.uniform(1.0, 1.05, n)
+    hs = h0[:, None] * grow[:, None] ** np.arange(layers)[None, :]
+    z = np.concatenate([z0[:, None], z0[:, None] + np.cumsum(hs, axis=1)], axis=1)
+    scale = z0 * 10.0 ** rng.uniform(-3, 3, n)
+    x = rng.standard_normal(n) * scale
+    y = rng.standard_normal(n) * scale
+    x[rng.random(n) < 0.1] = 0.0
+    y[rng.random(n) < 0.1] = 0.0
+    return x, y, z
+
+
+def test_atan_addition_formula_down_a_column():
+    # atan(u_k) = atan(u_0) + sum_j atan(delta_j) along a column, delta_j the
+    # atan-difference argument of segment j: u_j u_{j+1} >= 0, so no branch of
+    # atan is crossed, and all delta_j of a column share one sign (u is monotone
+    # in z), so their atan terms add up to |atan(u_k) - atan(u_0)| <= pi/2.
+    rng = np.random.default_rng(14)
+    x, y, z = _column_walk(rng, 50_000, 147)
+    s = (x * x + y * y)[:, None]
+    r = np.sqrt(s + z * z)
+    u = (x * y)[:, None] / (z * r)
+    u1, u2 = u[:, :-1], u[:, 1:]
+    assert np.all(u1 * u2 >= 0)
+    delta = np.arctan((u2 - u1) / (1.0 + u1 * u2))
+    walked = np.arctan(u[:, :1]) + np.cumsum(delta, axis=1)
+    assert np.abs(walked - np.arctan(u2)).max() <= 1e-13
+    same_sign = (np.all(delta <= 0, axis=1) | np.all(delta >= 0, axis=1))
+    assert np.all(same_sign)
+    assert np.abs(delta).sum(axis=1).max() <= np.pi / 2 * (1 + 1e-12)
+    # the closed form of delta used by the sweeps (no difference of u's)
+    z1, z2 = z[:, :-1], z[:, 1:]
+    hz = (z2 - z1) * (z1 + z2)
+    num = -(x * y)[:, None] * hz * (s + z1 * z1 + z2 * z2)
+    den = (z1 * r[:, :-1] + z2 * r[:, 1:]) * (z1 * r[:, :-1] * z2 * r[:, 1:] + ((x * y) ** 2)[:, None])
+    closed = np.arctan(num / den)
+    assert np.abs(closed - delta).max() <= 1e-14
+
+
+def test_fp32_carried_angle_error_in_sixteen_layer_walks():
+    # The adjoint carries the angle in FP32 over walks of at most 16 layers:
+    # A_{j+1} = fl32(A_j + fl32(atan(delta_j))).  With correctly rounded terms the
+    # error of A after j steps is at most sum of the half-ulp roundings,
+    # 2^-24 (|A_0| + sum_i |A_{i+1}| + sum_i |atan(delta_i)|).
+    rng = np.random.default_rng(15)
+    x, y, z = _column_walk(rng, 100_000, 16)
+    r = np.sqrt((x * x + y * y)[:, None] + z * z)
+    exact = np.arctan((x * y)[:, None] / (z * r))
+    a = exact[:, 0].astype(np.float32)
+    bound = 2.0 ** -24 * np.abs(exact[:, 0])
+    worst = 0.0
+    for j in range(16):
+        d = (exact[:, j + 1] - exact[:, j]).astype(np.float32)
+        a = (a + d).astype(np.float32)
+        bound = bound + 2.0 ** -24 * (np.abs(exact[:, j + 1]) + np.abs(exact[:, j + 1] - exact[:, j]))
+        err = np.abs(a.astype(np.float64) - exact[:, j + 1])
+        assert np.all(err <= bound * (1 + 1e-6) + 1e-30)
+        worst = max(worst, float((err / np.maximum(np.abs(exact[:, 0]), 1e-30)).max()))
+    # relative to the walk's largest angle (its first: |u| falls with depth)
+    # that is at most 33 roundings; in practice a few
+    assert worst < 33 * 2.0 ** -24
