@@ -3,15 +3,18 @@
 // the matrix cores.
 //
 // Per workgroup: 64 observations x all 64 (padded) models and one chunk of
-// consecutive kPBX x kPBY prism-column blocks; the layers are the outer loop
-// and the chunk's blocks the inner one.  One block step (one layer of one
-// block):
-//   1. VALU: edge-segment terms S of the block's vertical edges for the 64
-//      observations -> LDS.  Consecutive blocks along y share an edge row, and
-//      the LDS rows form a ring, so a step evaluates only the (kPBX+1) x kPBY
-//      new edges: 20 for the 16 prisms of a 4 x 4 block (1.25 per prism,
-//      five per wave), all 25 at the start of a chunk or a block row.  Both
-//      end nodes of each segment are formed in the step.
+// consecutive kPBX x kPBY prism-column blocks; the layers are the outer loop,
+// two per step, and the chunk's blocks the inner one.  One block step (two
+// layers of one block):
+//   1. VALU: edge-segment terms S of the block's vertical edges in both
+//      layers for the 64 observations -> LDS.  Consecutive blocks along y
+//      share an edge row, and the LDS rows form a ring, so a step evaluates
+//      only the (kPBX+1) x kPBY new edges: 20 for the 16 prisms of a 4 x 4
+//      block (1.25 per prism, five per wave), all 25 at the start of a chunk
+//      or a block row.  Each edge takes three nodes for its two segments, and
+//      the angle atan(u) of the middle node, evaluated for the upper segment,
+//      is carried to the lower one by the addition formula of atan.
+//   Then per layer of the step:
 //   2. VALU: per prism G = S00 - S10 - S01 + S11 (the (x, y) vertex parity of
 //      Eq. 1), split into bf16 hi = bf16(G), lo = bf16(G - hi) -> LDS in the
 //      MFMA A-operand order (obs x prisms).
@@ -20,9 +23,9 @@
 //      (FP32 accumulation), 16 prisms per instruction, B = the models
 //      pre-split into bf16 hi/lo and packed so that each lane loads its 8
 //      operands with one 16-byte load, issued after step 2.
-// Every kFlushBlocks block steps and at the end of each layer the FP32
-// accumulators are added into per-thread FP64 accumulators (four in
-// registers, twelve in LDS), so FP32 sums at most 512 prism terms.  The
+// Every kFlushBlocks layer steps and at the end of each pair of layers the
+// FP32 accumulators are added into per-thread FP64 accumulators (some in
+// registers, the rest in LDS), so FP32 sums at most 512 prism terms.  The
 // GRAV_FP32_VALU variant keeps steps 1-2 (G in FP32) and contracts on the
 // vector ALUs.
 #include <hip/hip_runtime.h>
@@ -100,49 +103,54 @@ __global__ void k_pack_models_f32(const float *__restrict__ models, int K, int n
     }
 }
 
+// FP64 accumulators per thread held in registers (the other 16 - n in LDS):
+// as many as keep the block's LDS within a quarter of the CU's 160 KiB (four
+// blocks of four waves per CU), the MFMA kernel holding less LDS than the
+// VALU kernel's model tile.
 #ifndef GRAV_MULTI_REG_ACC
-#define GRAV_MULTI_REG_ACC 4
+#define GRAV_MULTI_REG_ACC 5
 #endif
-constexpr int kRegAcc = GRAV_MULTI_REG_ACC;   // FP64 accumulators per thread held in registers
-static_assert(kRegAcc >= 0 && kRegAcc < 16, "at least one accumulator lives in LDS");
+constexpr int kRegAccMfma = GRAV_MULTI_REG_ACC;
+constexpr int kRegAccValu = 8;
+static_assert(kRegAccMfma >= 1 && kRegAccMfma < 16, "at least one accumulator lives in LDS");
 
 // Accumulator v of thread t (v is a compile-time index after unrolling).
-__device__ __forceinline__ double &acc_ref(double (&r)[kRegAcc > 0 ? kRegAcc : 1],
-                                           double (&lds)[16 - kRegAcc][256], int v, int t) {
-    return v < kRegAcc ? r[v] : lds[v - kRegAcc][t];
+template <int kRA>
+__device__ __forceinline__ double &acc_ref(double (&r)[kRA], double (&lds)[16 - kRA][256], int v,
+                                           int t) {
+    return v < kRA ? r[v] : lds[v - kRA][t];
 }
 
 // The FP32 accumulators (MFMA or VALU) are added into the FP64 ones after
-// this many block steps and at the end of every layer, so an FP32 sum holds at
-// most kFlushBlocks * kPrismsPerStep prism terms.
+// this many layer steps of a block and at the end of every pair of layers, so
+// an FP32 sum holds at most kFlushBlocks * kPrismsPerStep prism terms.
 constexpr int kFlushBlocks = 32;
 
 template <bool kMfma>
-__global__ __launch_bounds__(256) void k_forward_multi(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_forward_multi(
     const double *__restrict__ xn, const double *__restrict__ yn, const double *__restrict__ zn,
     int nx, int ny, int nz, const float *__restrict__ hk, const double *__restrict__ ox,
     const double *__restrict__ oy, const double *__restrict__ oz, int64_t n,
     const __bf16 *__restrict__ bhi, const __bf16 *__restrict__ blo,
     const float *__restrict__ b32, int nby, int64_t nblk, int64_t blocks_per_chunk, int nchunk,
     double *__restrict__ partial) {
-    // edge terms of the current block step: [y slot][x edge][observation]; the
-    // y slots form a ring, so the last edge row of one block is the first of
-    // the next block along y without being copied.  The MFMA kernel takes
-    // eight slots (slot arithmetic is a mask), the VALU kernel, which holds
-    // more LDS, the five it needs.
-    constexpr int kRingRows = kMfma ? 8 : kEdgeY;
-    static_assert(kEdgeY <= 8 && kPBY < kEdgeY, "a block's edge rows fit the ring");
-    auto ring = [](int x) { return kMfma ? (x & 7) : (x >= kEdgeY ? x - kEdgeY : x); };
-    __shared__ float sS[kRingRows][kEdgeX][kTileObs];
+    // edge terms of the current block step: [layer of the step][y slot][x
+    // edge][observation]; the kEdgeY y slots form a ring, so the last edge row
+    // of one block is the first of the next block along y without being copied
+    // (slot indices stay below 2 kEdgeY, so one subtraction wraps them)
+    static_assert(kPBY < kEdgeY, "a block's edge rows fit the ring");
+    auto ring = [](int x) { return x >= kEdgeY ? x - kEdgeY : x; };
+    __shared__ float sS[2][kEdgeY][kEdgeX][kTileObs];
     __shared__ __attribute__((aligned(16))) __bf16 sAhi[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) __bf16 sAlo[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sA32[kTileObs][kPrismsPerStep];
     __shared__ __attribute__((aligned(16))) float sB32[kPrismsPerStep][kModels];
-    // per-thread FP64 accumulators: the first kRegAcc in registers, the rest
-    // in LDS (column t), which keeps the block's LDS small enough for four
-    // blocks per CU
-    __shared__ double sAcc[16 - kRegAcc][256];
-    double rAcc[kRegAcc > 0 ? kRegAcc : 1];
+    // per-thread FP64 accumulators: the first kRA in registers, the rest in
+    // LDS (column t), which keeps the block's LDS small enough for four blocks
+    // per CU
+    constexpr int kRA = kMfma ? kRegAccMfma : kRegAccValu;
+    __shared__ double sAcc[16 - kRA][256];
+    double rAcc[kRA];
 
     const int chunk = (int)(blockIdx.x % nchunk);
     const int64_t tile = blockIdx.x / nchunk;
@@ -168,32 +176,39 @@ __global__ __launch_bounds__(256) void k_forward_multi(
     for (int v = 0; v < 16; ++v) {
         acc[v] = 0.0f;
         acc32[v] = 0.0f;
-        acc_ref(rAcc, sAcc, v, t) = 0.0;
+        acc_ref<kRA>(rAcc, sAcc, v, t) = 0.0;
     }
     auto flush = [&]() {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             if (kMfma) {
-                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc[v]);
+                acc_ref<kRA>(rAcc, sAcc, v, t) += static_cast<double>(acc[v]);
                 acc[v] = 0.0f;
             } else {
-                acc_ref(rAcc, sAcc, v, t) += static_cast<double>(acc32[v]);
+                acc_ref<kRA>(rAcc, sAcc, v, t) += static_cast<double>(acc32[v]);
                 acc32[v] = 0.0f;
             }
         }
     };
 
-    // Layers outside, the chunk's prism-column blocks inside: consecutive
-    // blocks along y share an edge row, so a block step evaluates the
-    // kEdgeX x kPBY new edges only (4 x 4 block: 20 edge terms for 16 prisms,
+    // Layers outside (two per step), the chunk's prism-column blocks inside:
+    // consecutive blocks along y share an edge row, so a block step evaluates
+    // the kEdgeX x kPBY new edges only (4 x 4 block: 20 edges for 16 prisms,
     // 1.25 per prism, five per wave), and the full kEdgeX x kEdgeY at the
-    // start of a chunk or of a block row.  Both end nodes of a segment are
-    // formed here (no carry along z across block steps).
-    for (int k = 0; k < nz; ++k) {
+    // start of a chunk or of a block row.  Each edge is walked over the two
+    // layers k, k + 1 of the step: three nodes instead of four, and the angle
+    // atan(u) of the middle node, evaluated for layer k, is carried to the
+    // bottom node by the addition formula (atan(u2) = atan(u1) + atan(delta),
+    // u1 u2 >= 0), so the second segment needs no range-reduced atan of its
+    // own.  The middle node lies at least one layer below the mesh top (z > 0).
+    for (int k = 0; k < nz; k += 2) {
+        const bool two = k + 1 < nz;    // uniform; the last step of an odd nz has one layer
         const float zt = static_cast<float>(zn[k] - zo);
-        const float zb = static_cast<float>(zn[k + 1] - zo);
-        const float h = hk[k];
-        const bool deep = k >= kdeep;   // uniform: deep layers take the shorter formula
+        const float zm = static_cast<float>(zn[k + 1] - zo);
+        const float zb = two ? static_cast<float>(zn[k + 2] - zo) : zm;
+        const float h0 = hk[k];
+        const float h1 = two ? hk[k + 1] : 0.0f;
+        const bool deep0 = k >= kdeep, deep1 = k + 1 >= kdeep;   // uniform
         int slot0 = 0;                  // ring slot of the block's first edge row
         int nacc = 0;
         float cxr[kEdgeX];              // x offsets of the current block row's edges
@@ -213,10 +228,10 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             } else {
                 slot0 = ring(slot0 + kPBY);
             }
-            // phase 1: edge terms S of edge row q (y node j0 + q) at the x
-            // edges ii with (ii mod 4) == wv, or at all of them
-            auto edge_row = [&](auto deepc, int q, bool all_x) {
-                constexpr bool kDeep = decltype(deepc)::value;
+            // phase 1: edge terms S of both layers for edge row q (y node
+            // j0 + q) at the x edges ii with (ii mod 4) == wv, or at all of them
+            auto edge_row = [&](auto d0, auto d1, int q, bool all_x) {
+                constexpr bool kD0 = decltype(d0)::value, kD1 = decltype(d1)::value;
                 const int b = j0 + q;
                 const bool vy = b <= ny;
                 const float cy = column_offset(yn[vy ? b : ny], yo);
@@ -226,93 +241,112 @@ __global__ __launch_bounds__(256) void k_forward_multi(
                     if (all_x || (ii & 3) == wv) {
                         const Column col = column_from_xy(cxr[ii], cy);
                         const Node top = make_node(col, zt);
+                        const Node mid = make_node(col, zm);
                         const Node bot = make_node(col, zb);
-                        const float S = edge_segment<kDeep>(col, top, bot, h);
-                        sS[slot][ii][lo_] = (vx[ii] && vy) ? S : 0.0f;
+                        float lnY, lnX;
+                        const float hz0 = h0 * (top.z + mid.z);
+                        edge_logs<kD0>(col, top, mid, hz0, lnY, lnX);
+                        const float A = fm::atan_ratio(col.xy, mid.zR);
+                        const float atd0 = edge_atan_delta<kD0>(col, top, mid, hz0);
+                        const float S0 = edge_assemble<kD0>(col, top, h0, A, atd0, lnY, lnX);
+                        const float hz1 = h1 * (mid.z + bot.z);
+                        edge_logs<kD1>(col, mid, bot, hz1, lnY, lnX);
+                        const float atd1 = edge_atan_delta<kD1>(col, mid, bot, hz1);
+                        const float S1 = edge_assemble<kD1>(col, mid, h1, A + atd1, atd1, lnY, lnX);
+                        const bool valid = vx[ii] && vy;
+                        sS[0][slot][ii][lo_] = valid ? S0 : 0.0f;
+                        sS[1][slot][ii][lo_] = valid ? S1 : 0.0f;
                     }
                 }
             };
-            auto phase1 = [&](auto deepc) {
+            auto phase1 = [&](auto d0, auto d1) {
                 // wave wv owns the new edge row q = wv + 1 (kPBY == 4 waves)
-                edge_row(deepc, wv + 1, true);
-                if (fresh) edge_row(deepc, 0, false);
+                edge_row(d0, d1, wv + 1, true);
+                if (fresh) edge_row(d0, d1, 0, false);
             };
-            if (deep)
-                phase1(std::true_type{});
+            if (deep0)
+                phase1(std::true_type{}, std::true_type{});
+            else if (deep1)
+                phase1(std::false_type{}, std::true_type{});
             else
-                phase1(std::false_type{});
-            __syncthreads();
-            // phase 2: prism terms of prism rows ii = wv, wv + 4, ... (all jj)
-            // for observation lo_.  A row's kPBY prisms are stored with one
-            // vector write per array (scattered 2-byte writes to rows 32 bytes
-            // apart conflict on the LDS banks).
+                phase1(std::false_type{}, std::false_type{});
+            for (int L = 0; L < (two ? 2 : 1); ++L) {
+                const int kl = k + L;
+                // L = 0: the edge terms are complete; L = 1: every wave is
+                // done reading layer k's prism terms before they are replaced
+                __syncthreads();
+                // phase 2: prism terms of prism rows ii = wv, wv + 4, ... (all
+                // jj) for observation lo_.  A row's kPBY prisms are stored with
+                // one vector write per array (scattered 2-byte writes to rows
+                // 32 bytes apart conflict on the LDS banks).
 #pragma unroll
-            for (int r = 0; r < kPBX / 4; ++r) {
-                const int ii = wv + 4 * r;
-                __bf16 hi4[kPBY], lo4[kPBY];
-                float g4[kPBY];
+                for (int r = 0; r < kPBX / 4; ++r) {
+                    const int ii = wv + 4 * r;
+                    __bf16 hi4[kPBY], lo4[kPBY];
+                    float g4[kPBY];
 #pragma unroll
-                for (int q = 0; q < kPBY; ++q) {
-                    const int s0 = ring(slot0 + q), s1 = ring(slot0 + q + 1);
-                    float G = (sS[s0][ii][lo_] - sS[s0][ii + 1][lo_]) -
-                              (sS[s1][ii][lo_] - sS[s1][ii + 1][lo_]);
-                    G = (i0 + ii < nx && j0 + q < ny) ? G : 0.0f;
-                    g4[q] = G;
-                    hi4[q] = static_cast<__bf16>(G);
-                    lo4[q] = static_cast<__bf16>(G - static_cast<float>(hi4[q]));
+                    for (int q = 0; q < kPBY; ++q) {
+                        const int s0 = ring(slot0 + q), s1 = ring(slot0 + q + 1);
+                        float G = (sS[L][s0][ii][lo_] - sS[L][s0][ii + 1][lo_]) -
+                                  (sS[L][s1][ii][lo_] - sS[L][s1][ii + 1][lo_]);
+                        G = (i0 + ii < nx && j0 + q < ny) ? G : 0.0f;
+                        g4[q] = G;
+                        hi4[q] = static_cast<__bf16>(G);
+                        lo4[q] = static_cast<__bf16>(G - static_cast<float>(hi4[q]));
+                    }
+                    const int p0 = ii * kPBY;
+                    if (kMfma) {
+                        *reinterpret_cast<bf16x4 *>(&sAhi[lo_][p0]) = *reinterpret_cast<bf16x4 *>(hi4);
+                        *reinterpret_cast<bf16x4 *>(&sAlo[lo_][p0]) = *reinterpret_cast<bf16x4 *>(lo4);
+                    } else {
+                        *reinterpret_cast<float4 *>(&sA32[lo_][p0]) = *reinterpret_cast<float4 *>(g4);
+                    }
                 }
-                const int p0 = ii * kPBY;
+                if (!kMfma) {
+                    const float4 *src = reinterpret_cast<const float4 *>(
+                        b32 + ((blk * nz + kl) * kPrismsPerStep) * kModels);
+                    for (int q = t; q < kPrismsPerStep * kModels / 4; q += 256)
+                        reinterpret_cast<float4 *>(&sB32[0][0])[q] = src[q];
+                }
+                // this layer's model operands: loaded here, after the edge and
+                // prism terms, they wait at the barrier instead of holding
+                // eight registers through phase 1
+                bf16x8 bh[kKSteps], bl[kKSteps];
                 if (kMfma) {
-                    *reinterpret_cast<bf16x4 *>(&sAhi[lo_][p0]) = *reinterpret_cast<bf16x4 *>(hi4);
-                    *reinterpret_cast<bf16x4 *>(&sAlo[lo_][p0]) = *reinterpret_cast<bf16x4 *>(lo4);
+                    const int l = lo_;
+                    const int64_t bo =
+                        ((blk * nz + kl) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
+#pragma unroll
+                    for (int kk = 0; kk < kKSteps; ++kk) {
+                        bh[kk] = *reinterpret_cast<const bf16x8 *>(bhi + bo + 16 * kk);
+                        bl[kk] = *reinterpret_cast<const bf16x8 *>(blo + bo + 16 * kk);
+                    }
+                }
+                __syncthreads();
+                // phase 3: contraction over the prisms of this layer step
+                if (kMfma) {
+                    const int l = lo_;
+#pragma unroll
+                    for (int kk = 0; kk < kKSteps; ++kk) {
+                        const int kc = 16 * kk + (l >> 5) * 8;
+                        const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(&sAhi[r0 + (l & 31)][kc]);
+                        const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(&sAlo[r0 + (l & 31)][kc]);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bh[kk], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bl[kk], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bh[kk], acc, 0, 0, 0);
+                    }
                 } else {
-                    *reinterpret_cast<float4 *>(&sA32[lo_][p0]) = *reinterpret_cast<float4 *>(g4);
-                }
-            }
-            if (!kMfma) {
-                const float4 *src = reinterpret_cast<const float4 *>(
-                    b32 + ((blk * nz + k) * kPrismsPerStep) * kModels);
-                for (int q = t; q < kPrismsPerStep * kModels / 4; q += 256)
-                    reinterpret_cast<float4 *>(&sB32[0][0])[q] = src[q];
-            }
-            // this step's model operands: loaded here, after the edge and
-            // prism terms, they wait at the barrier instead of holding eight
-            // registers through phase 1
-            bf16x8 bh[kKSteps], bl[kKSteps];
-            if (kMfma) {
-                const int l = lo_;
-                const int64_t bo =
-                    ((blk * nz + k) * kModels + c0 + (l & 31)) * kPrismsPerStep + (l >> 5) * 8;
 #pragma unroll
-                for (int kk = 0; kk < kKSteps; ++kk) {
-                    bh[kk] = *reinterpret_cast<const bf16x8 *>(bhi + bo + 16 * kk);
-                    bl[kk] = *reinterpret_cast<const bf16x8 *>(blo + bo + 16 * kk);
-                }
-            }
-            __syncthreads();
-            // phase 3: contraction over the prisms of this step
-            if (kMfma) {
-                const int l = lo_;
+                    for (int p = 0; p < kPrismsPerStep; ++p) {
+                        const float gp = sA32[lo_][p];
 #pragma unroll
-                for (int kk = 0; kk < kKSteps; ++kk) {
-                    const int kc = 16 * kk + (l >> 5) * 8;
-                    const bf16x8 ahi = *reinterpret_cast<const bf16x8 *>(&sAhi[r0 + (l & 31)][kc]);
-                    const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(&sAlo[r0 + (l & 31)][kc]);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bh[kk], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bl[kk], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bh[kk], acc, 0, 0, 0);
+                        for (int v = 0; v < 16; ++v) acc32[v] = fmaf(gp, sB32[p][wv * 16 + v], acc32[v]);
+                    }
                 }
-            } else {
-#pragma unroll
-                for (int p = 0; p < kPrismsPerStep; ++p) {
-                    const float gp = sA32[lo_][p];
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) acc32[v] = fmaf(gp, sB32[p][wv * 16 + v], acc32[v]);
+                if (++nacc == kFlushBlocks) {
+                    flush();
+                    nacc = 0;
                 }
-            }
-            if (++nacc == kFlushBlocks) {
-                flush();
-                nacc = 0;
             }
             if (++bj == nby) {
                 bj = 0;
@@ -329,12 +363,13 @@ __global__ __launch_bounds__(256) void k_forward_multi(
             const int row = r0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
             const int64_t og = tile * kTileObs + row;
             if (og < n)
-                partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] = acc_ref(rAcc, sAcc, v, t);
+                partial[((int64_t)chunk * n + og) * kModels + c0 + (l & 31)] =
+                    acc_ref<kRA>(rAcc, sAcc, v, t);
         }
     } else if (o < n) {
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-            partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = acc_ref(rAcc, sAcc, v, t);
+            partial[((int64_t)chunk * n + o) * kModels + wv * 16 + v] = acc_ref<kRA>(rAcc, sAcc, v, t);
     }
 }
 

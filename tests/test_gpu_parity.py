@@ -182,8 +182,9 @@ def test_single_prism_singular_and_far_positions(g, ctx, prec_name):
     dict(seed=5, nx=13, ny=11, nz=7, n=333, on_nodes=20, on_top=40),
     dict(seed=6, nx=31, ny=17, nz=19, n=70, on_nodes=5, on_top=5),
     dict(seed=7, nx=2, ny=3, nz=1, n=1, on_nodes=1, on_top=1),
-    # 40 layers, first deep layer 12: chunks of 14, 13, 13 layers starting at
-    # 0, 14, 27, the last two on the deep-layer path with an odd layer count
+    # 40 layers, first deep layer 12: the 12 layers above it in one chunk on
+    # the general path, the deep ones in two chunks of 14 (layers 12-25 and
+    # 26-39), each walk carrying its angle over 14 layers
     dict(seed=13, nx=9, ny=8, nz=40, n=61, on_nodes=5, on_top=5),
 ])
 def test_adjoint_random_ragged(g, ctx, prec_name, case):
@@ -209,6 +210,43 @@ def test_adjoint_random_ragged(g, ctx, prec_name, case):
             _check_termwise(label, gt, ref, scale, informative=not signed)
 
 
+def _first_deep_layer(zn, ratio=9.0, min_depth=1e-3):
+    """First layer from which every layer's top lies at least `ratio`
+    thicknesses and `min_depth` below the mesh top."""
+    k = len(zn) - 1
+    while k > 0 and zn[k - 1] - zn[0] >= ratio * (zn[k] - zn[k - 1]) and zn[k - 1] - zn[0] >= min_depth:
+        k -= 1
+    return k
+
+
+@pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
+def test_adjoint_graded_layers_two_general_chunks(g, ctx, prec_name):
+    """Layers 3 m thick, one of 8 m at index 16, then 4 m: the first deep
+    layer is 17, so the mixed adjoint chunks the 17 layers above it in two
+    (9 and 8 layers) and the 33 deep ones in three walks of 11 (odd length),
+    which fill all ceil(50 / 16) + 1 chunk indices of the launch."""
+    p = workloads.random_case(21, 8, 7, 1, 61, on_nodes=5, on_top=5)
+    hz = np.array([3.0] * 16 + [8.0] + [4.0] * 33)
+    zn = np.concatenate([[0.0], np.cumsum(hz)])
+    assert _first_deep_layer(zn) == 17
+    m = workloads.Mesh(p.mesh.xn, p.mesh.yn, zn)
+    mesh = g.DeviceMesh.from_mesh(m)
+    obs = g.DeviceObs.from_survey(p.obs)
+    prec = getattr(g, prec_name)
+    cells = np.arange(m.ncells)
+    for probe, signed in ((np.abs(p.probe_v), False), (p.probe_v, True)):
+        gt = to_np(ctx.adjoint(mesh, obs, _t(probe), prec=prec))
+        ref = prism.adjoint(m, p.obs, probe)
+        label = f"adjoint graded {prec_name} {'signed' if signed else '|v|'}"
+        if prec_name == "GRAV_FP64":
+            err = rel_l2(gt, ref)
+            _report(label, err)
+            assert err <= TOL_F64
+        else:
+            scale = prism.adjoint_abs_scale(m, p.obs, probe, cells)
+            _check_termwise(label, gt, ref, scale, informative=not signed)
+
+
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
 def test_adjoint_dot_product(g, ctx, prec_name):
     """<G m, v> = <m, G^T v> on the GPU operators themselves."""
@@ -227,8 +265,8 @@ def test_adjoint_dot_product(g, ctx, prec_name):
 @pytest.mark.parametrize("prec_name", ["GRAV_FP64", "GRAV_MIXED"])
 @pytest.mark.parametrize("case", [
     (9, 12, 10, 8, 150),
-    # 40 layers, first deep layer 12: the adjoint's layer chunks start at 0,
-    # 14 and 27, two of them on the deep-layer path
+    # 40 layers, first deep layer 12: the adjoint's layer chunks start at 0
+    # (general path), 12 and 26 (deep-layer path)
     (13, 9, 8, 40, 61),
 ])
 def test_dataspace_apply_matches_oracle(g, ctx, prec_name, case):
