@@ -302,12 +302,15 @@ int grav_server::step(std::vector<Request *> &reqs) {
         q->phase = Phase::CG;
     }
     // ---- batched adjoint sweep (requests by decreasing tile cost: observations
-    // per part x layers per chunk)
+    // per part x layers per chunk, taken as ceil(nz / ceil(nz / 16)); the plan
+    // has one chunk index more for the split at the first deep layer, which is
+    // known on the device only)
     std::vector<Request *> order;
     for (Request *q : reqs)
         if (q->phase == Phase::CG || q->phase == Phase::Final) order.push_back(q);
     auto adj_tile_cost = [](const Request *q) {
-        return q->ap.obs_per_part * (int64_t)((q->g.nz + q->ap.nkc - 1) / q->ap.nkc);
+        const int nch = q->ap.nkc - 1;
+        return q->ap.obs_per_part * (int64_t)((q->g.nz + nch - 1) / nch);
     };
     std::stable_sort(order.begin(), order.end(), [&](const Request *a, const Request *b) {
         return adj_tile_cost(a) > adj_tile_cost(b);
