@@ -606,6 +606,11 @@ def _blocky_models(mesh, K, seed):
     dict(seed=21, nx=9, ny=6, nz=5, n=130, K=5),
     dict(seed=22, nx=17, ny=13, nz=11, n=70, K=64),
     dict(seed=23, nx=4, ny=4, nz=2, n=64, K=1),
+    # one layer: the kernel's only layer step holds a single layer
+    dict(seed=25, nx=6, ny=5, nz=1, n=80, K=3),
+    # 23 layers, first deep layer 12: general and deep layer pairs, and a last
+    # step with one deep layer
+    dict(seed=27, nx=7, ny=6, nz=23, n=100, K=64),
 ])
 def test_forward_multi_per_model(g, ctx, prec_name, case):
     import torch
