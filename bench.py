@@ -67,12 +67,10 @@ def slots(instr: int, trans: int) -> int:
 
 
 def adjoint_deep_chunks(nz: int, kdeep: int) -> int:
-    """Layer chunks of the mixed adjoint that start at or below the first deep
-    layer (the library's plan: ceil(nz / 16) chunks, the first nz mod chunks
-    one layer longer)."""
-    nkc = -(-nz // ADJ_LAYERS)
-    kq, kr = divmod(nz, nkc)
-    return sum(1 for kc in range(nkc) if kc * kq + min(kc, kr) >= kdeep)
+    """Layer chunks of the mixed adjoint over the deep layers (the library's
+    plan chunks the layers above the first deep one and the deep ones
+    separately, at most 16 layers a chunk)."""
+    return -(-(nz - kdeep) // ADJ_LAYERS)
 
 
 def sweep_costs(n: int, ncols: int, nz: int, kdeep: int):
