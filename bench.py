@@ -487,6 +487,7 @@ def run_profile_op(args) -> int:
         "adjoint": ("adjoint_mixed", lambda c: c.adjoint(mesh, obs, v, out_m, prec=g.GRAV_MIXED)),
         "dataspace": ("adjoint_mixed", lambda c: c.dataspace_apply(mesh, obs, w, 1e-12, v, out_n,
                                                                    prec=g.GRAV_MIXED)),
+        "trace": ("trace_mixed", lambda c: c.trace(mesh, obs, w, prec=g.GRAV_MIXED)),
     }
     if args.profile_op == "multi":
         # 64 density models on the 100 x 100 x 50 mesh with 10,000 stations
@@ -598,7 +599,7 @@ def main() -> int:
                     help="measure the instruction issue rates behind the roofline weights")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--profile-op", choices=("forward", "adjoint", "dataspace", "multi"),
+    ap.add_argument("--profile-op", choices=("forward", "adjoint", "dataspace", "multi", "trace"),
                     help="only time this operator at paper scale (profiling runs)")
     ap.add_argument("--serve-extras-requests", type=int, default=60,
                     help="requests of the serving stream replayed in the default run (0 = none)")
